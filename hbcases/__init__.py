@@ -1,0 +1,145 @@
+"""Case definitions and seeded synthetic inputs shared by the tests, the smoke
+check and the benchmark.
+
+This module holds no arithmetic of the method: only problem parameters (the
+cavity workloads of the HB-UGKS paper's Section 3 at the sizes the benchmark
+uses) and seeded random numbers.  Both the CPU oracle and the GPU path take
+their inputs from here; neither is imported by this module.
+
+Units: rho0 = H = sqrt(2 R T0) = 1 (T in units of T0, velocities in
+sqrt(2 R T0)).  Walls are ordered bottom (y=0), right (x=L), top (y=H),
+left (x=0); each wall row is (ut_mean, ut_re, ut_im, T_mean, T_re, T_im), so
+the wall value is mean + Re(hat * exp(i omega t)) as in Eqs. (25)-(26).
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional, Sequence
+
+import numpy as np
+
+REST_WALLS = ((0.0, 0.0, 0.0, 1.0, 0.0, 0.0),) * 4
+
+
+def lid_walls(amplitude=0.01):
+    """Top lid moving tangentially with amplitude * cos(omega t); walls at T0."""
+    w = [list(r) for r in REST_WALLS]
+    w[2][1] = amplitude
+    return tuple(tuple(r) for r in w)
+
+
+def thermal_walls(dT=0.5, wall=0, phase="sin"):
+    """One wall with T = T0 (1 + dT sin(omega t)) (or cos), others at T0, all at rest."""
+    w = [list(r) for r in REST_WALLS]
+    if phase == "sin":
+        w[wall][5] = -dT  # Re(-i dT e^{i wt}) = dT sin(wt)
+    else:
+        w[wall][4] = dT
+    return tuple(tuple(r) for r in w)
+
+
+@dataclass(frozen=True)
+class Case:
+    nx: int
+    ny: int
+    M: int
+    umax: float
+    Kn: float
+    St: float
+    NH: int
+    walls: tuple = REST_WALLS
+    L: float = 1.0
+    H: float = 1.0
+    x_faces: Optional[Sequence[float]] = None
+    y_faces: Optional[Sequence[float]] = None
+    cfl: float = 0.5
+    face_dt: int = 0          # 0 = min of the two cells, 1 = harmonic mean (Eq. 33)
+    Pr: float = 2.0 / 3.0     # Shakhov; 1.0 = BGK
+    omega_vss: float = 0.81
+    alpha_vss: float = 1.0
+    K: int = 1                # internal degrees of freedom
+    macro_mode: int = 0       # 0 = macro flux of Eq. (24); 1 = all-discrete sum of the micro flux
+    dt_mode: int = 0          # 0 = local pseudo step (Eqs. 31-32); 1 = global step dt_fixed
+    dt_fixed: float = 0.0
+    name: str = field(default="", compare=False)
+
+    @property
+    def NT(self):
+        return 2 * self.NH + 1
+
+    @property
+    def nc(self):
+        return self.nx * self.ny
+
+    @property
+    def nv(self):
+        return self.M * self.M
+
+    @property
+    def updates(self):
+        """cell x velocity x level updates per pseudo step."""
+        return self.nc * self.nv * self.NT
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+# ----------------------------------------------------------------- workloads
+def shear_small():
+    """FP64 correctness case: 16x16 cells, 16x16 velocities on [-4,4], BGK,
+    NH=1, Kn=1, St=1, lid 0.01 cos(wt), isothermal walls."""
+    return Case(16, 16, 16, 4.0, 1.0, 1.0, 1, lid_walls(0.01), Pr=1.0, name="shear16_v16_nh1")
+
+
+def shear_cavity(Kn=1.0, St=1.0):
+    """Benchmark case: 64x64 cells, 32x32 velocities on [-4,4], NH=1, lid 0.01, Shakhov."""
+    return Case(64, 64, 32, 4.0, Kn, St, 1, lid_walls(0.01),
+                name=f"shear64_v32_nh1_kn{Kn:g}_st{St:g}")
+
+
+SHEAR_KN = (0.01, 0.1, 1.0, 10.0)
+SHEAR_ST = (0.1, 1.0, 10.0)
+
+
+def thermal_cavity(Kn=1.0, St=1.0):
+    """Mixed-precision case: 64x64 cells, 48x48 velocities on [-5,5], NH=4,
+    bottom wall T = T0 (1 + 0.5 sin wt), Shakhov."""
+    return Case(64, 64, 48, 5.0, Kn, St, 4, thermal_walls(0.5, 0, "sin"),
+                name=f"thermal64_v48_nh4_kn{Kn:g}_st{St:g}")
+
+
+THERMAL_KN = (0.05, 1.0)
+THERMAL_ST = (1.0, 10.0)
+
+
+def batch_sweep(n=64, seed=260503479):
+    """Seeded heterogeneous sweep: grid side U{24..96}, velocity side U{24..48}
+    (rounded up to even), NH U{1..4}, Kn log-uniform [0.01, 10], St log-uniform
+    [0.1, 10]; half shear (lid 0.01, [-4,4]) and half thermal (bottom wall,
+    dT U(0.1, 0.5), [-5,5])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        N = int(rng.integers(24, 97))
+        M = int(rng.integers(24, 49))
+        M += M % 2
+        NH = int(rng.integers(1, 5))
+        Kn = float(10.0 ** rng.uniform(-2.0, 1.0))
+        St = float(10.0 ** rng.uniform(-1.0, 1.0))
+        if k % 2 == 0:
+            out.append(Case(N, N, M, 4.0, Kn, St, NH, lid_walls(0.01), name=f"batch{k}_shear"))
+        else:
+            dT = float(rng.uniform(0.1, 0.5))
+            out.append(Case(N, N, M, 5.0, Kn, St, NH, thermal_walls(dT, 0, "sin"),
+                            name=f"batch{k}_thermal"))
+    return out
+
+
+# ----------------------------------------------------------------- seeded noise
+def noise(shape, seed, scale=1.0):
+    """Seeded standard-normal numbers times `scale` (PCG64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return scale * rng.standard_normal(shape)
+
+
+def uniform(shape, seed, lo=-1.0, hi=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(lo, hi, shape)
