@@ -1,0 +1,155 @@
+/*
+ * hb_ugks.h -- C ABI of the MI355X HB-UGKS pseudo-step library.
+ *
+ * The library advances the time-domain harmonic-balance unified gas-kinetic
+ * scheme (HB-UGKS, arXiv 2605.03479, Sec. 2) for one 2-D cavity case on one
+ * AMD Instinct GPU (gfx950).  The state is the macroscopic W and the reduced
+ * distributions (h, b) of Sec. 2.1 (Eqs. 7-8) at every cell, discrete velocity
+ * and sub-time level n = 0..2*NH (Eq. 12); one pseudo step (Sec. 2.4,
+ * Eqs. 29-33) updates all of them at once.
+ *
+ * Units are the paper's nondimensional ones with rho0 = H = sqrt(2 R T0) = 1:
+ * velocities in sqrt(2 R T0), temperatures in T0, lengths in H, omega = St
+ * (Eq. 37), mu(T0) from Kn by Eq. (36).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (HB_OK) on success, a negative HB_E* code on failure;
+ *     hb_ugks_strerror() names the code;
+ *   - host pointers are owned by the caller and only read/written during the
+ *     call; the handle owns all device memory it allocates (hipMalloc);
+ *   - a handle is not thread-safe; distinct handles are independent;
+ *   - work is queued on the handle's stream (the one given at creation, or
+ *     the null stream); calls that return host data synchronise that stream.
+ * Host array layouts (row-major, last index fastest):
+ *   W[c][n][4]  (rho, rho U, rho V, rho E), c = j*nx + i (x fastest)
+ *   h, b[c][n][a]  a = iv*M + iu, node u_k = -umax + k*2*umax/(M-1)
+ */
+#ifndef HB_UGKS_H
+#define HB_UGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HB_OK = 0,
+    HB_EINVAL = -1,     /* an argument is out of range (sizes, Kn <= 0, NULL, ...) */
+    HB_ENOMEM = -2,     /* device allocation failed or exceeds hbm_budget_bytes */
+    HB_ESTATE = -3,     /* call out of order (e.g. pseudo_step before set_case) */
+    HB_EDIVERGED = -4,  /* NaN/Inf in the residual: the state is kept for state_out */
+    HB_EDEVICE = -5,    /* a HIP runtime call failed, or no gfx950 device */
+    HB_ECAPACITY = -6   /* the caller's buffer is too small */
+};
+
+typedef enum { HB_FP64 = 0, HB_MIXED = 1 } hb_precision;
+
+typedef struct hb_ugks *hb_handle;
+
+typedef struct {
+    int device;               /* HIP device ordinal */
+    void *stream;             /* hipStream_t to queue work on; NULL = null stream */
+    int precision;            /* hb_precision; HB_MIXED keeps h, b and the per-velocity
+                                 flux/source arithmetic in FP32, moments, W and the
+                                 residual in FP64 */
+    size_t hbm_budget_bytes;  /* 0 = no limit */
+} hb_create_opts;
+
+typedef struct {
+    double L, H;              /* cavity [0,L] x [0,H] */
+    int nx, ny;               /* cells, >= 3 each */
+    const double *x_faces;    /* NULL = uniform, else nx+1 increasing coordinates */
+    const double *y_faces;    /* NULL = uniform, else ny+1 increasing coordinates */
+} hb_geometry;
+
+/* One wall; order bottom (y=0), right (x=L), top (y=H), left (x=0).
+ * Tangential velocity is along +x for bottom/top and +y for left/right.
+ * Sub-level values follow Eqs. (25)-(26): mean + Re(hat * exp(i omega t_n)). */
+typedef struct {
+    double ut_mean, ut_hat_re, ut_hat_im;
+    double T_mean, T_hat_re, T_hat_im;
+} hb_wall;
+
+/* Square tensor velocity grid: m nodes per axis on [-umax, umax] with the
+ * closed composite trapezoid rule (m even, 4 <= m <= 128). */
+typedef struct {
+    int m;
+    double umax;
+} hb_vgrid;
+
+typedef struct {
+    double cfl;               /* Eq. (31); default 0.5 */
+    int face_dt;              /* Eq. (33): 0 = min of the two cells, 1 = harmonic mean */
+    double Pr;                /* Shakhov Prandtl number (Eq. 4); 1 = BGK; default 2/3 */
+    double omega_vss;         /* mu ~ T^omega_vss; default 0.81 */
+    double alpha_vss;         /* VSS scattering parameter of Eq. (36); default 1 */
+    int K_int;                /* internal degrees of freedom (Eq. 3); default 1 */
+    int dt_mode;              /* 0 = local pseudo steps (Eqs. 31-32), 1 = global step dt_fixed */
+    double dt_fixed;
+} hb_numerics;
+
+/* Defaults: cfl 0.5, face_dt 0, Pr 2/3, omega_vss 0.81, alpha_vss 1, K_int 1, dt_mode 0. */
+void hb_ugks_default_numerics(hb_numerics *out);
+
+/* Create a handle on opts->device (NULL opts = device 0, null stream, FP64).
+ * Errors: HB_EINVAL (out NULL, bad precision), HB_EDEVICE (no such device or
+ * not gfx950). */
+int hb_ugks_create(const hb_create_opts *opts, hb_handle *out);
+
+/* Define the case and reset the state to the uniform rest Maxwellian
+ * (rho = 1, U = 0, T = T0 at every level).  Kn (Eq. 36) and St (Eq. 37) set
+ * mu(T0) and omega; n_harmonics = NH gives NT = 2 NH + 1 levels (NT <= 11).
+ * walls: 4 entries; num: NULL = defaults.  Allocates the device state.
+ * Errors: HB_EINVAL (sizes, Kn <= 0, St < 0, odd m, non-increasing faces,
+ * cfl <= 0), HB_ENOMEM, HB_EDEVICE. */
+int hb_ugks_set_case(hb_handle h, const hb_geometry *geo, double Kn, double St, int n_harmonics,
+                     const hb_wall walls[4], const hb_vgrid *vg, const hb_numerics *num);
+
+/* Queue nsteps pseudo steps (Sec. 2.4 with the UGKS flux of Sec. 2.2 and the
+ * walls of Sec. 2.3) on the handle's stream; returns without synchronising.
+ * Errors: HB_ESTATE (no case), HB_EINVAL (nsteps < 0), HB_EDEVICE. */
+int hb_ugks_pseudo_step(hb_handle h, int nsteps);
+
+/* Residual of the last completed step, Eq. (43): RMS over cells of the
+ * level-0 change of (rho, rho U, rho V, rho E).  Synchronises the stream.
+ * step_index (may be NULL) receives the number of steps taken.
+ * Errors: HB_ESTATE, HB_EDIVERGED (NaN/Inf seen in any step since set_case). */
+int hb_ugks_residual(hb_handle h, double out[4], long *step_index);
+
+/* Fourier coefficients of Eq. (40), qhat_k = (1/NT) sum_n q_n exp(-i k omega t_n),
+ * k = 0..NH, of the variables selected by var_mask bits:
+ *   0 rho, 1 U, 2 V, 3 T/T0 (from W), 4 P_xy (Eq. 39, from h about U_n, V_n),
+ *   5 q_x, 6 q_y (Eq. 6 from h, b about U_n, V_n).
+ * re/im layout [selected var in bit order][k][c]; capacity = doubles in each
+ * of re and im.  Synchronises.  Errors: HB_ESTATE, HB_ECAPACITY, HB_EINVAL. */
+int hb_ugks_harmonics_out(hb_handle h, unsigned var_mask, double *re, double *im, size_t capacity);
+
+/* Copy the state out / in (FP64, host layouts above; any pointer may be NULL
+ * to skip that array).  capacity = doubles available in h (and in b); W needs
+ * nc*NT*4.  In HB_MIXED, h and b are converted.  Synchronises.
+ * Errors: HB_ESTATE, HB_ECAPACITY. */
+int hb_ugks_state_out(hb_handle h, double *W, double *hh, double *bb, size_t capacity);
+int hb_ugks_state_in(hb_handle h, const double *W, const double *hh, const double *bb);
+
+/* Sizes of the current case: out[0..5] = nx, ny, nc, M, nv (= M*M), NT. */
+int hb_ugks_sizes(hb_handle h, int out[6]);
+
+/* Device bytes held by the handle. */
+size_t hb_ugks_device_bytes(hb_handle h);
+
+/* Per-kernel timing: when enabled, every pseudo step records HIP events
+ * around each of its kernels on the handle's stream; hb_ugks_kernel_times
+ * synchronises and returns, per kernel of the step (in launch order), its
+ * name, number of launches and summed milliseconds since timing was enabled.
+ * Errors: HB_ESTATE, HB_ECAPACITY (fewer than the step's kernels). */
+int hb_ugks_enable_timing(hb_handle h, int on);
+int hb_ugks_kernel_times(hb_handle h, const char **names, long *launches, double *ms, int capacity);
+
+void hb_ugks_destroy(hb_handle h);
+const char *hb_ugks_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

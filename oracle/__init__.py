@@ -56,6 +56,7 @@ def lib():
         L.hbref_constants.argtypes = [ctypes.c_void_p, _D]
         L.hbref_max_nu.restype = ctypes.c_double
         L.hbref_max_nu.argtypes = [ctypes.c_void_p]
+        L.hbref_set_dt_scale.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.hbref_time.restype = ctypes.c_double
         L.hbref_time.argtypes = [ctypes.c_void_p]
         L.hbref_E.argtypes = [ctypes.c_int, _D]
@@ -172,6 +173,10 @@ class Oracle:
 
     def time(self):
         return lib().hbref_time(self._h)
+
+    def set_dt_scale(self, s):
+        """Test hook: multiply every local pseudo step by s."""
+        lib().hbref_set_dt_scale(self._h, float(s))
 
     def max_nu(self):
         return lib().hbref_max_nu(self._h)

@@ -59,6 +59,7 @@ typedef struct {
     double *sxh, *syh, *sxb, *syb;
     double *Fx, *Fy; /* macro fluxes [face][n][4], x-faces (nx+1)*ny, y-faces nx*(ny+1) */
     double t_phys;   /* time-domain mode: physical time */
+    double dt_scale; /* test hook: multiplies every local step (1 by default) */
 } hbref;
 
 /* ------------------------------------------------------------------ */
@@ -535,6 +536,7 @@ int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, 
         }
     o->step = 0;
     o->t_phys = 0.0;
+    o->dt_scale = 1.0;
     memset(o->res, 0, sizeof(o->res));
     return 0;
 }
@@ -985,7 +987,7 @@ static void one_step(hbref *o, int with_E)
     double om = with_E ? o->omega : 0.0;
 
     /* local pseudo steps from W^k, Eqs. (31)-(32) */
-    for (int c = 0; c < nc; c++) o->dtc[c] = local_dt(o, c);
+    for (int c = 0; c < nc; c++) o->dtc[c] = local_dt(o, c) * o->dt_scale;
     /* heat flux q^k of h^k, b^k about U^k (Shakhov term of h+^k) */
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < nc; c++)
@@ -1108,7 +1110,9 @@ void hbref_get_debug(void *p, double *dtc, double *Fx, double *Fy)
     if (Fy) memcpy(Fy, o->Fy, sizeof(double) * o->nx * (o->ny + 1) * o->NT * 4);
 }
 
-/* Set the local steps of the next call of the macro flux only (debug). */
+/* Test hook: scale every local pseudo step by s (e.g. 1 + 2^-52 to measure
+ * how strongly the converged state reacts to one ulp of perturbation). */
+void hbref_set_dt_scale(void *p, double s) { ((hbref *)p)->dt_scale = s; }
 
 /* ------------------------------------------------------------------ */
 /* Harmonics, Eq. (40): qhat_k = (1/NT) sum_n q_n exp(-i k omega t_n), for

@@ -1,0 +1,255 @@
+"""MI355X-native HB-UGKS pseudo-step engine.
+
+The work runs in the gfx950 HIP library ``libhbugks.so`` behind the C ABI of
+``include/hb_ugks.h``; this module only marshals arguments through ctypes
+(same entry-point names) and wraps a handle in :class:`Solver`.  There is no
+CPU fallback: if the library is missing, loading fails loudly.
+
+Host layouts: W[c][n][4], h/b[c][n][alpha], c = j*nx + i, alpha = iv*M + iu.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_ESTATE, HB_EDIVERGED, HB_EDEVICE, HB_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+HB_FP64, HB_MIXED = 0, 1
+VARS = ("rho", "U", "V", "T", "Pxy", "qx", "qy")
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+class hb_create_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class hb_geometry(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("H", ctypes.c_double), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("x_faces", _D), ("y_faces", _D)]
+
+
+class hb_wall(ctypes.Structure):
+    _fields_ = [("ut_mean", ctypes.c_double), ("ut_hat_re", ctypes.c_double), ("ut_hat_im", ctypes.c_double),
+                ("T_mean", ctypes.c_double), ("T_hat_re", ctypes.c_double), ("T_hat_im", ctypes.c_double)]
+
+
+class hb_vgrid(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("umax", ctypes.c_double)]
+
+
+class hb_numerics(ctypes.Structure):
+    _fields_ = [("cfl", ctypes.c_double), ("face_dt", ctypes.c_int), ("Pr", ctypes.c_double),
+                ("omega_vss", ctypes.c_double), ("alpha_vss", ctypes.c_double), ("K_int", ctypes.c_int),
+                ("dt_mode", ctypes.c_int), ("dt_fixed", ctypes.c_double)]
+
+
+EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
+           "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
+           "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
+           "hb_ugks_destroy", "hb_ugks_strerror")
+
+_LIB = None
+
+
+def load_library(path=None):
+    """Load libhbugks.so (never builds; raises if it is absent)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or _build.LIB
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library {p} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(p)
+    vp, ip, dp, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.hb_ugks_default_numerics.argtypes = [ctypes.POINTER(hb_numerics)]
+    L.hb_ugks_default_numerics.restype = None
+    L.hb_ugks_create.argtypes = [ctypes.POINTER(hb_create_opts), ctypes.POINTER(vp)]
+    L.hb_ugks_set_case.argtypes = [vp, ctypes.POINTER(hb_geometry), dp, dp, ip, ctypes.POINTER(hb_wall),
+                                   ctypes.POINTER(hb_vgrid), ctypes.POINTER(hb_numerics)]
+    L.hb_ugks_pseudo_step.argtypes = [vp, ip]
+    L.hb_ugks_residual.argtypes = [vp, _D, ctypes.POINTER(ctypes.c_long)]
+    L.hb_ugks_harmonics_out.argtypes = [vp, ctypes.c_uint, _D, _D, sz]
+    L.hb_ugks_state_out.argtypes = [vp, _D, _D, _D, sz]
+    L.hb_ugks_state_in.argtypes = [vp, _D, _D, _D]
+    L.hb_ugks_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.hb_ugks_device_bytes.argtypes = [vp]
+    L.hb_ugks_device_bytes.restype = sz
+    L.hb_ugks_enable_timing.argtypes = [vp, ip]
+    L.hb_ugks_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_long), _D, ip]
+    L.hb_ugks_destroy.argtypes = [vp]
+    L.hb_ugks_destroy.restype = None
+    L.hb_ugks_strerror.argtypes = [ip]
+    L.hb_ugks_strerror.restype = ctypes.c_char_p
+    for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_residual",
+                 "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
+                 "hb_ugks_enable_timing", "hb_ugks_kernel_times"):
+        getattr(L, name).restype = ctypes.c_int
+    if path is None:
+        _LIB = L
+    return L
+
+
+class HBError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = load_library().hb_ugks_strerror(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def _check(code, what):
+    if code < 0:
+        raise HBError(code, what)
+    return code
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+# ------------------------------------------------------------- C-ABI mirrors
+def hb_ugks_create(device=0, stream=None, precision=HB_FP64, hbm_budget_bytes=0):
+    o = hb_create_opts(device, stream, precision, hbm_budget_bytes)
+    h = ctypes.c_void_p()
+    _check(load_library().hb_ugks_create(ctypes.byref(o), ctypes.byref(h)), "hb_ugks_create")
+    return h
+
+
+def default_numerics():
+    n = hb_numerics()
+    load_library().hb_ugks_default_numerics(ctypes.byref(n))
+    return n
+
+
+def hb_ugks_set_case(h, case):
+    """case: an object with the fields of hbcases.Case."""
+    xf = None if case.x_faces is None else np.ascontiguousarray(case.x_faces, np.float64)
+    yf = None if case.y_faces is None else np.ascontiguousarray(case.y_faces, np.float64)
+    g = hb_geometry(case.L, case.H, case.nx, case.ny, _dp(xf), _dp(yf))
+    walls = (hb_wall * 4)(*[hb_wall(*map(float, w)) for w in case.walls])
+    vg = hb_vgrid(case.M, case.umax)
+    nm = hb_numerics(case.cfl, case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K, case.dt_mode,
+                     case.dt_fixed)
+    return _check(load_library().hb_ugks_set_case(h, ctypes.byref(g), case.Kn, case.St, case.NH, walls,
+                                                   ctypes.byref(vg), ctypes.byref(nm)), "hb_ugks_set_case")
+
+
+def hb_ugks_pseudo_step(h, nsteps):
+    return _check(load_library().hb_ugks_pseudo_step(h, int(nsteps)), "hb_ugks_pseudo_step")
+
+
+def hb_ugks_residual(h):
+    out = np.zeros(4)
+    k = ctypes.c_long()
+    rc = load_library().hb_ugks_residual(h, _dp(out), ctypes.byref(k))
+    return rc, out, k.value
+
+
+def hb_ugks_sizes(h):
+    s = (ctypes.c_int * 6)()
+    _check(load_library().hb_ugks_sizes(h, s), "hb_ugks_sizes")
+    return tuple(s)
+
+
+def hb_ugks_harmonics_out(h, var_mask=0x7F):
+    nx, ny, nc, M, nv, NT = hb_ugks_sizes(h)
+    nsel = bin(var_mask & 0x7F).count("1")
+    NH = (NT - 1) // 2
+    re = np.zeros((nsel, NH + 1, nc))
+    im = np.zeros((nsel, NH + 1, nc))
+    _check(load_library().hb_ugks_harmonics_out(h, var_mask, _dp(re), _dp(im), re.size), "hb_ugks_harmonics_out")
+    return re, im
+
+
+def hb_ugks_state_out(h):
+    nx, ny, nc, M, nv, NT = hb_ugks_sizes(h)
+    W = np.zeros((nc, NT, 4))
+    hh = np.zeros((nc, NT, nv))
+    bb = np.zeros((nc, NT, nv))
+    _check(load_library().hb_ugks_state_out(h, _dp(W), _dp(hh), _dp(bb), hh.size), "hb_ugks_state_out")
+    return W, hh, bb
+
+
+def hb_ugks_state_in(h, W, hh, bb):
+    nx, ny, nc, M, nv, NT = hb_ugks_sizes(h)
+    W = None if W is None else np.ascontiguousarray(W, np.float64).reshape(-1)
+    hh = None if hh is None else np.ascontiguousarray(hh, np.float64).reshape(-1)
+    bb = None if bb is None else np.ascontiguousarray(bb, np.float64).reshape(-1)
+    for a, n in ((W, nc * NT * 4), (hh, nc * NT * nv), (bb, nc * NT * nv)):
+        if a is not None and a.size != n:
+            raise ValueError("state array of the wrong size")
+    return _check(load_library().hb_ugks_state_in(h, _dp(W), _dp(hh), _dp(bb)), "hb_ugks_state_in")
+
+
+def hb_ugks_enable_timing(h, on=True):
+    return _check(load_library().hb_ugks_enable_timing(h, int(on)), "hb_ugks_enable_timing")
+
+
+def hb_ugks_kernel_times(h):
+    cap = 16
+    names = (ctypes.c_char_p * cap)()
+    launches = (ctypes.c_long * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = _check(load_library().hb_ugks_kernel_times(h, names, launches, ms, cap), "hb_ugks_kernel_times")
+    return {names[k].decode(): (launches[k], ms[k]) for k in range(n)}
+
+
+def hb_ugks_device_bytes(h):
+    return load_library().hb_ugks_device_bytes(h)
+
+
+def hb_ugks_destroy(h):
+    load_library().hb_ugks_destroy(h)
+
+
+class Solver:
+    """One case on one GPU: create + set_case; methods mirror the C ABI."""
+
+    def __init__(self, case, device=0, stream=None, precision=HB_FP64, hbm_budget_bytes=0):
+        self.case = case
+        self.h = hb_ugks_create(device, stream, precision, hbm_budget_bytes)
+        try:
+            hb_ugks_set_case(self.h, case)
+        except Exception:
+            hb_ugks_destroy(self.h)
+            self.h = None
+            raise
+        self.sizes = hb_ugks_sizes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            hb_ugks_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def step(self, n=1):
+        hb_ugks_pseudo_step(self.h, n)
+
+    def residual(self):
+        rc, r, k = hb_ugks_residual(self.h)
+        _check(rc, "hb_ugks_residual")
+        return r
+
+    def step_index(self):
+        return hb_ugks_residual(self.h)[2]
+
+    def state(self):
+        return hb_ugks_state_out(self.h)
+
+    def set_state(self, W, h, b):
+        hb_ugks_state_in(self.h, W, h, b)
+
+    def harmonics(self, var_mask=0x7F):
+        return hb_ugks_harmonics_out(self.h, var_mask)
+
+    def enable_timing(self, on=True):
+        hb_ugks_enable_timing(self.h, on)
+
+    def kernel_times(self):
+        return hb_ugks_kernel_times(self.h)
+
+    def device_bytes(self):
+        return hb_ugks_device_bytes(self.h)

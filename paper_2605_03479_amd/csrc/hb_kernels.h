@@ -1,0 +1,827 @@
+// HIP kernels of one HB-UGKS pseudo step on gfx950 (FP64 form).
+//
+// Data layout (device):
+//   h, b [cell][level][alpha']  alpha' = quadrant-major velocity order: each
+//       quadrant (sign u, sign v) is a contiguous, 64-padded block, so every
+//       wavefront holds velocities of one quadrant and all its lanes share the
+//       upwind side of every face.  Adjacent lanes = adjacent velocities.
+//   W    [cell][level][4]
+//   feed [cell][level][FEED]   per-cell velocity moments for the faces it feeds
+//   recx [x-face][level][REC], recy [y-face][level][REC]  face records
+//   crec [cell][level][CREC]   equilibria of W^k and W^{k+1} for the collision
+// Kernels per step: moments -> faces -> cells -> residual -> update.
+#include "hb_device.h"
+#include "hb_layout.h"
+
+namespace hb {
+
+// Block -> cell map that gives each XCD (blocks are dealt round-robin to the
+// 8 XCDs) a contiguous range of cells, so stencil neighbours share its L2.
+__device__ inline int xcd_cell(int b, int G)
+{
+    int x = b & 7, k = b >> 3;
+    int per = G >> 3, rem = G & 7;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ inline double vanleer(double a, double b)
+{
+    double p = a * b;
+    return p > 0.0 ? 2.0 * p / (a + b) : 0.0;
+}
+
+// Slope along one line of cells at index i (len cells), f(k) = base[k * stride];
+// one-sided at the two wall-adjacent cells, van Leer inside.
+__device__ inline double line_slope(const double *__restrict__ base, long stride, int i, int len, double fi,
+                                    const double *__restrict__ rc)
+{
+    if (i == 0) return (base[stride] - fi) * rc[1];
+    if (i == len - 1) return (fi - base[(long)(i - 1) * stride]) * rc[i];
+    double sm = (fi - base[(long)(i - 1) * stride]) * rc[i];
+    double sp = (base[(long)(i + 1) * stride] - fi) * rc[i + 1];
+    return vanleer(sm, sp);
+}
+
+// ---------------------------------------------------------------- K1: moments
+// One block per cell, wave q = velocity quadrant q (u>0: bit 0, v>0: bit 1).
+// Per level, each lane accumulates over its velocities the FEED sums for the
+// x-face and y-face its quadrant is upwind of, plus the cell moments; the
+// wave reduces them through LDS (transpose + row sums) and the four waves
+// combine into the per-face feeds.
+#define K1_ROW 65
+__global__ __launch_bounds__(256) void k_moments(Params P, const double *__restrict__ h,
+                                                 const double *__restrict__ b, double *__restrict__ feed)
+{
+    __shared__ double red[4][28 * K1_ROW];
+    __shared__ double wsum[4][NMOM];
+    const int c = xcd_cell(blockIdx.x, gridDim.x);
+    const int i = c % P.nx, j = c / P.nx;
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int NT = P.NT;
+    const long sx = (long)NT * P.nvp;        // x-neighbour stride
+    const long sy = (long)P.nx * NT * P.nvp;  // y-neighbour stride
+    const double dxo = (q & 1) ? (P.xf[i + 1] - P.xc[i]) : (P.xf[i] - P.xc[i]);
+    const double dyo = (q & 2) ? (P.yf[j + 1] - P.yc[j]) : (P.yf[j] - P.yc[j]);
+
+    for (int n = 0; n < NT; n++) {
+        double acc[NMOM];
+#pragma unroll
+        for (int k = 0; k < NMOM; k++) acc[k] = 0.0;
+        for (int r = lane; r < P.Qp; r += 64) {
+            const int ap = q * P.Qp + r;
+            const double u = P.vu[ap], v = P.vv[ap], w = P.vw[ap];
+            const long e = ((long)c * NT + n) * P.nvp + ap;
+            const double hc = h[e], bc = b[e];
+            const double sxh = line_slope(h + e - i * sx, sx, i, P.nx, hc, P.rcx);
+            const double sxb = line_slope(b + e - i * sx, sx, i, P.nx, bc, P.rcx);
+            const double syh = line_slope(h + e - j * sy, sy, j, P.ny, hc, P.rcy);
+            const double syb = line_slope(b + e - j * sy, sy, j, P.ny, bc, P.rcy);
+            const double uu = u * u, uv = u * v, vv = v * v;
+            const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
+                                   w * vv * v};
+            const double r2 = uu + vv;
+            const double sh = u * sxh + v * syh, sb = u * sxb + v * syb;
+            // x-feed: face-normal u, tangential slope sigma_y
+            const double h0x = hc + sxh * dxo, b0x = bc + sxb * dxo;
+#pragma unroll
+            for (int k = 0; k < 10; k++) acc[k] += wm[k] * h0x;
+            acc[10] += wm[0] * b0x;
+            acc[11] += wm[1] * b0x;
+            acc[12] += wm[2] * b0x;
+            acc[13] += wm[0] * syh;
+            acc[14] += wm[1] * syh;
+            acc[15] += wm[2] * syh;
+            acc[16] += 0.5 * (w * r2 * syh + w * syb);
+            acc[17] += wm[1] * sh;
+            acc[18] += wm[3] * sh;
+            acc[19] += wm[4] * sh;
+            acc[20] += 0.5 * wm[1] * (r2 * sh + sb);
+            // y-feed: face-normal v, tangential slope sigma_x
+            const double h0y = hc + syh * dyo, b0y = bc + syb * dyo;
+#pragma unroll
+            for (int k = 0; k < 10; k++) acc[21 + k] += wm[k] * h0y;
+            acc[31] += wm[0] * b0y;
+            acc[32] += wm[1] * b0y;
+            acc[33] += wm[2] * b0y;
+            acc[34] += wm[0] * sxh;
+            acc[35] += wm[1] * sxh;
+            acc[36] += wm[2] * sxh;
+            acc[37] += 0.5 * (w * r2 * sxh + w * sxb);
+            acc[38] += wm[2] * sh;
+            acc[39] += wm[4] * sh;
+            acc[40] += wm[5] * sh;
+            acc[41] += 0.5 * wm[2] * (r2 * sh + sb);
+            // cell moments of h^k, b^k
+#pragma unroll
+            for (int k = 0; k < 10; k++) acc[42 + k] += wm[k] * hc;
+            acc[52] += wm[0] * bc;
+            acc[53] += wm[1] * bc;
+            acc[54] += wm[2] * bc;
+        }
+        // wave reduction in two halves through LDS: lane k sums row k
+        double *rb = red[q];
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            const int k0 = half * 28, kn = half ? NMOM - 28 : 28;
+#pragma unroll
+            for (int k = 0; k < 28; k++)
+                if (k < kn) rb[k * K1_ROW + lane] = acc[k0 + k];
+            __syncthreads();
+            if (lane < kn) {
+                double s = 0.0;
+                for (int l = 0; l < 64; l++) s += rb[lane * K1_ROW + l];
+                wsum[q][k0 + lane] = s;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        // combine quadrants: E = q1 + q3, W = q0 + q2, N = q2 + q3, S = q0 + q1
+        double *out = feed + ((long)c * NT + n) * FEED;
+        for (int t = threadIdx.x; t < FEED; t += blockDim.x) {
+            double val;
+            if (t < 21) val = wsum[1][t] + wsum[3][t];
+            else if (t < 42) val = wsum[0][t - 21] + wsum[2][t - 21];
+            else if (t < 63) val = wsum[2][t - 42 + 21] + wsum[3][t - 42 + 21];
+            else if (t < 84) val = wsum[0][t - 63 + 21] + wsum[1][t - 63 + 21];
+            else val = ((wsum[0][t - 84 + 42] + wsum[1][t - 84 + 42]) + wsum[2][t - 84 + 42]) + wsum[3][t - 84 + 42];
+            out[t] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- K2: faces
+// Face-frame raw moments -> W0, primitives, heat flux.
+struct FaceState {
+    double rho, Un, Ut, lam, qn, qt, W[4];
+};
+__device__ inline void face_state(int K, const double m[10], const double mb[3], FaceState &s)
+{
+    s.W[0] = m[0];
+    s.W[1] = m[1];
+    s.W[2] = m[2];
+    s.W[3] = 0.5 * (m[3] + m[5]) + 0.5 * mb[0];
+    double p[4];
+    prim4(K, s.W, p);
+    s.rho = p[0];
+    s.Un = p[1];
+    s.Ut = p[2];
+    s.lam = p[3];
+    const double Un = s.Un, Ut = s.Ut;
+    double mu30 = m[6] - 3.0 * Un * m[3] + 3.0 * Un * Un * m[1] - Un * Un * Un * m[0];
+    double mu12 = m[8] - 2.0 * Ut * m[4] + Ut * Ut * m[1] - Un * (m[5] - 2.0 * Ut * m[2] + Ut * Ut * m[0]);
+    double mu21 = m[7] - 2.0 * Un * m[4] + Un * Un * m[2] - Ut * (m[3] - 2.0 * Un * m[1] + Un * Un * m[0]);
+    double mu03 = m[9] - 3.0 * Ut * m[5] + 3.0 * Ut * Ut * m[2] - Ut * Ut * Ut * m[0];
+    s.qn = 0.5 * (mu30 + mu12 + mb[1] - Un * mb[0]);
+    s.qt = 0.5 * (mu21 + mu03 + mb[2] - Ut * mb[0]);
+}
+
+// 1-D sums G[k] = sum_i w_i x_i^k exp(-lam (x_i - U)^2), k = 0..6, over nodes
+// with sign selection sel (0 all, 1 x>0, 2 x<0).
+__device__ inline void gsums(const Params &P, double lam, double U, int sel, double G[7])
+{
+#pragma unroll
+    for (int k = 0; k < 7; k++) G[k] = 0.0;
+    for (int k = 0; k < P.M; k++) {
+        const double x = P.u1[k];
+        if ((sel == 1 && !(x > 0.0)) || (sel == 2 && !(x < 0.0))) continue;
+        double t = P.w1[k] * exp(-lam * (x - U) * (x - U));
+#pragma unroll
+        for (int p = 0; p < 7; p++) {
+            G[p] += t;
+            t *= x;
+        }
+    }
+}
+
+// sum_alpha w u_n psi (H0 + H0+, B0 + B0+) from the 1-D sums of the face Maxwellian.
+__device__ inline void equil_flux_sums(int K, double pref, double lam, const P3 &Ph, const P3 &Pb, const double *Gn,
+                                       const double *Gt, double S[4])
+{
+    S[0] = pref * p3_sum(Ph, 1, 0, Gn, Gt);
+    S[1] = pref * p3_sum(Ph, 2, 0, Gn, Gt);
+    S[2] = pref * p3_sum(Ph, 1, 1, Gn, Gt);
+    S[3] = pref * (0.5 * (p3_sum(Ph, 3, 0, Gn, Gt) + p3_sum(Ph, 1, 2, Gn, Gt)) +
+                   0.5 * (K / (2.0 * lam)) * p3_sum(Pb, 1, 0, Gn, Gt));
+}
+
+__device__ inline void store_side(double *rec, int side, double lam, double Un, double Ut, const P3 &Qh, const P3 &Qb,
+                                  double c4, double c5)
+{
+    double *s = rec + REC_SIDE + REC_SIDEW * side;
+    s[0] = lam;
+    s[1] = Un;
+    s[2] = Ut;
+#pragma unroll
+    for (int k = 0; k < 10; k++) {
+        s[3 + k] = Qh.c[k];
+        s[13 + k] = Qb.c[k];
+    }
+    s[23] = c4;
+    s[24] = c5;
+}
+
+// one thread per (face, level); x-faces first, then y-faces
+__global__ __launch_bounds__(128) void k_faces(Params P, const double *__restrict__ feed,
+                                               const double *__restrict__ W, const double *__restrict__ dtc,
+                                               double *__restrict__ recx, double *__restrict__ recy)
+{
+    const int NT = P.NT, nx = P.nx, ny = P.ny, K = P.K;
+    const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (nfx + nfy) * NT) return;
+    const int n = t % NT;
+    int f = t / NT;
+    bool isx = f < nfx;
+    int cL, cR, lo_end;  // cells on the low/high side (-1 if wall)
+    double xL = 0, xF = 0, xR = 0;
+    double *rec;
+    if (isx) {
+        const int fi = f % (nx + 1), jj = f / (nx + 1);
+        cL = fi > 0 ? jj * nx + fi - 1 : -1;
+        cR = fi < nx ? jj * nx + fi : -1;
+        xF = P.xf[fi];
+        if (cL >= 0) xL = P.xc[fi - 1];
+        if (cR >= 0) xR = P.xc[fi];
+        lo_end = fi == 0;
+        rec = recx + ((long)f * NT + n) * REC;
+    } else {
+        f -= nfx;
+        const int ii = f % nx, fj = f / nx;
+        cL = fj > 0 ? (fj - 1) * nx + ii : -1;
+        cR = fj < ny ? fj * nx + ii : -1;
+        xF = P.yf[fj];
+        if (cL >= 0) xL = P.yc[fj - 1];
+        if (cR >= 0) xR = P.yc[fj];
+        lo_end = fj == 0;
+        rec = recy + ((long)f * NT + n) * REC;
+    }
+    // global -> face-frame index maps (y-faces: n = v, t = u)
+    const int p10x[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9}, p10y[10] = {0, 2, 1, 5, 4, 3, 9, 8, 7, 6};
+    const int p3x[3] = {0, 1, 2}, p3y[3] = {0, 2, 1};
+    const int p4x[4] = {0, 1, 2, 3}, p4y[4] = {0, 2, 1, 3};
+    const int *p10 = isx ? p10x : p10y;
+    const int *p3i = isx ? p3x : p3y;
+    const int *p4 = isx ? p4x : p4y;
+    // feeds: low cell feeds through its high face (E or N), high cell through its low face (W or S)
+    const int offHi = isx ? FEED_E : FEED_N, offLo = isx ? FEED_W : FEED_S;
+    double m[10], mb[3], ts[4], c5s[4];
+    {
+        const double *fa = cL >= 0 ? feed + ((long)cL * NT + n) * FEED + offHi : nullptr;
+        const double *fb = cR >= 0 ? feed + ((long)cR * NT + n) * FEED + offLo : nullptr;
+        double g[21];
+        for (int k = 0; k < 21; k++) g[k] = (fa ? fa[k] : 0.0) + (fb ? fb[k] : 0.0);
+        for (int k = 0; k < 10; k++) m[k] = g[p10[k]];
+        for (int k = 0; k < 3; k++) mb[k] = g[10 + p3i[k]];
+        for (int k = 0; k < 4; k++) ts[k] = g[13 + p4[k]];
+        for (int k = 0; k < 4; k++) c5s[k] = g[17 + p4[k]];
+    }
+    const double S4[4] = {m[1], m[3], m[4], 0.5 * (m[6] + m[8]) + 0.5 * mb[1]};
+    double F[4];
+
+    if (cL >= 0 && cR >= 0) {
+        // ---------------- interior face (Eqs. 21-24)
+        FaceState fs;
+        face_state(K, m, mb, fs);
+        const double rho = fs.rho, Un = fs.Un, Ut = fs.Ut, lam = fs.lam;
+        const double tau0 = tau_of(P, rho, lam);
+        const double dGL = dtc[cL], dGR = dtc[cR];
+        const double dGf = P.face_dt == 1 ? 2.0 * dGL * dGR / (dGL + dGR) : fmin(dGL, dGR);
+        double C[5];
+        ccoef(tau0, dGf, C);
+        double WL[4], WR[4];
+        {
+            const double *a = W + ((long)cL * NT + n) * 4, *bb = W + ((long)cR * NT + n) * 4;
+            for (int k = 0; k < 4; k++) {
+                WL[k] = a[p4[k]];
+                WR[k] = bb[p4[k]];
+            }
+        }
+        double dWL[4], dWR[4], dWt[4];
+        const double dL = xF - xL, dR = xR - xF;
+        for (int k = 0; k < 4; k++) {
+            dWL[k] = (fs.W[k] - WL[k]) / dL / rho;
+            dWR[k] = (WR[k] - fs.W[k]) / dR / rho;
+            dWt[k] = ts[k] / rho;
+        }
+        double aL[4], aR[4], at[4], A[4];
+        slope_solve(Un, Ut, lam, K, dWL, aL);
+        slope_solve(Un, Ut, lam, K, dWR, aR);
+        slope_solve(Un, Ut, lam, K, dWt, at);
+        MomTab t0, tp, tm;
+        momtab(Un, Ut, lam, K, 0, t0);
+        momtab(Un, Ut, lam, K, 1, tp);
+        momtab(Un, Ut, lam, K, 2, tm);
+        double r1[4], r2[4], r3[4], rhs[4];
+        mpsi_apsi(tp, 1, 0, aL, r1);
+        mpsi_apsi(tm, 1, 0, aR, r2);
+        mpsi_apsi(t0, 0, 1, at, r3);
+        for (int k = 0; k < 4; k++) rhs[k] = -(r1[k] + r2[k] + r3[k]);
+        slope_solve(Un, Ut, lam, K, rhs, A);
+        // macro flux
+        double c2a[4], c2b[4], c2c[4], c3[4];
+        mpsi_apsi(tp, 2, 0, aL, c2a);
+        mpsi_apsi(tm, 2, 0, aR, c2b);
+        mpsi_apsi(t0, 1, 1, at, c2c);
+        mpsi_apsi(t0, 1, 0, A, c3);
+        const double sq = (1.0 - P.Pr) * 4.0 * lam * lam / (5.0 * rho);
+        P3 Ph, Pb;
+        shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 5.0, Ph);
+        shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 3.0, Pb);
+        Ph.c[0] += 1.0;
+        Pb.c[0] += 1.0;
+        double Gn[7], Gt[7];
+        gsums(P, lam, Un, 0, Gn);
+        gsums(P, lam, Ut, 0, Gt);
+        const double pref = rho * lam / HB_PI;
+        double S1[4];
+        equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
+        for (int k = 0; k < 4; k++)
+            F[k] = (C[0] * S1[k] + C[1] * rho * (c2a[k] + c2b[k] + c2c[k]) + C[2] * rho * c3[k] + C[3] * S4[k] +
+                    C[4] * c5s[k]) /
+                   dGf;
+        // micro-flux records: side 1 (u_n > 0) uses a^L, side 0 uses a^R
+        const double xh = K / (2.0 * lam), xb = (K + 2.0) / (2.0 * lam);
+        const double ln[3] = {0.0, 1.0, 0.0}, lt[3] = {0.0, 0.0, 1.0}, l1[3] = {1.0, 0.0, 0.0};
+        double qt_h[6], qt_b[6], qA_h[6], qA_b[6];
+        apsi_quad(at, xh, qt_h);
+        apsi_quad(at, xb, qt_b);
+        apsi_quad(A, xh, qA_h);
+        apsi_quad(A, xb, qA_b);
+        P3 tTh, tTb, pAh, pAb;
+        p3_lin_quad(lt, qt_h, tTh);
+        p3_lin_quad(lt, qt_b, tTb);
+        p3_lin_quad(l1, qA_h, pAh);
+        p3_lin_quad(l1, qA_b, pAb);
+        for (int side = 0; side < 2; side++) {
+            const double *as = side ? aL : aR;
+            double qs_h[6], qs_b[6];
+            apsi_quad(as, xh, qs_h);
+            apsi_quad(as, xb, qs_b);
+            P3 nSh, nSb, Qh, Qb;
+            p3_lin_quad(ln, qs_h, nSh);
+            p3_lin_quad(ln, qs_b, nSb);
+            p3_zero(Qh);
+            p3_zero(Qb);
+            p3_axpy(C[0], Ph, Qh);
+            p3_axpy(C[1], nSh, Qh);
+            p3_axpy(C[1], tTh, Qh);
+            p3_axpy(C[2], pAh, Qh);
+            p3_axpy(C[0], Pb, Qb);
+            p3_axpy(C[1], nSb, Qb);
+            p3_axpy(C[1], tTb, Qb);
+            p3_axpy(C[2], pAb, Qb);
+            const double sh = pref / dGf, sbq = pref * xh / dGf;
+            for (int k = 0; k < 10; k++) {
+                Qh.c[k] *= sh;
+                Qb.c[k] *= sbq;
+            }
+            store_side(rec, side, lam, Un, Ut, Qh, Qb, C[3] / dGf, C[4] / dGf);
+        }
+    } else {
+        // ---------------- diffuse isothermal wall (Eqs. 25-28)
+        const int c = cL >= 0 ? cL : cR;
+        const int inc_side = lo_end ? 0 : 1;  // incident velocities: u.n_in < 0
+        const int refl_side = 1 - inc_side;
+        int wl;
+        if (isx) wl = lo_end ? 3 : 1;
+        else wl = lo_end ? 0 : 2;
+        const double Uw = P.wall_ut[wl][n], lw = 1.0 / P.wall_T[wl][n];
+        double Gwn[7], Gwt[7];
+        gsums(P, lw, 0.0, refl_side ? 1 : 2, Gwn);
+        gsums(P, lw, Uw, 0, Gwt);
+        const double pw = lw / HB_PI, xw = K / (2.0 * lw);
+        // reflected half of the unit-density wall Maxwellian: R_ab = sum w n^a t^b H_w
+        auto R = [&](int a, int bq) { return pw * Gwn[a] * Gwt[bq]; };
+        const double rw0 = -m[1] / R(1, 0);
+        double mc[10], mbc[3];
+        const int EN[10] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0}, ET[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+        for (int k = 0; k < 10; k++) mc[k] = m[k] + rw0 * R(EN[k], ET[k]);
+        for (int k = 0; k < 3; k++) mbc[k] = mb[k] + rw0 * xw * R(EN[k], ET[k]);
+        FaceState fs;
+        face_state(K, mc, mbc, fs);
+        const double rho = fs.rho, Un = fs.Un, Ut = fs.Ut, lam = fs.lam;
+        const double tau0 = tau_of(P, rho, lam);
+        const double dGf = dtc[c];
+        double C[5];
+        ccoef(tau0, dGf, C);
+        const double sq = (1.0 - P.Pr) * 4.0 * lam * lam / (5.0 * rho);
+        P3 Ph, Pb;
+        shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 5.0, Ph);
+        shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 3.0, Pb);
+        Ph.c[0] += 1.0;
+        Pb.c[0] += 1.0;
+        double Gn[7], Gt[7];
+        gsums(P, lam, Un, inc_side ? 1 : 2, Gn);
+        gsums(P, lam, Ut, 0, Gt);
+        const double pref = rho * lam / HB_PI;
+        double S1[4];
+        equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
+        const double inflow = (C[0] * S1[0] + C[3] * m[1] + C[4] * c5s[0]) / dGf;
+        const double rw = -inflow / R(1, 0);
+        const double Sr[4] = {R(1, 0), R(2, 0), R(1, 1), 0.5 * (R(3, 0) + R(1, 2)) + 0.5 * xw * R(1, 0)};
+        for (int k = 0; k < 4; k++) F[k] = rw * Sr[k] + (C[0] * S1[k] + C[3] * S4[k] + C[4] * c5s[k]) / dGf;
+        // records
+        P3 Qh, Qb;
+        for (int k = 0; k < 10; k++) {
+            Qh.c[k] = Ph.c[k] * pref * C[0] / dGf;
+            Qb.c[k] = Pb.c[k] * pref * (K / (2.0 * lam)) * C[0] / dGf;
+        }
+        store_side(rec, inc_side, lam, Un, Ut, Qh, Qb, C[3] / dGf, C[4] / dGf);
+        p3_zero(Qh);
+        p3_zero(Qb);
+        Qh.c[0] = rw * pw;
+        Qb.c[0] = rw * pw * xw;
+        store_side(rec, refl_side, lw, 0.0, Uw, Qh, Qb, 0.0, 0.0);
+    }
+    // macro flux in the global frame
+    if (isx) {
+        rec[0] = F[0];
+        rec[1] = F[1];
+        rec[2] = F[2];
+        rec[3] = F[3];
+    } else {
+        rec[0] = F[0];
+        rec[1] = F[2];
+        rec[2] = F[1];
+        rec[3] = F[3];
+    }
+}
+
+// ---------------------------------------------------------------- K3: cells
+__device__ inline void heat_flux_raw(const double *m, const double *mb, double U, double V, double q[2])
+{
+    double mu30 = m[6] - 3.0 * U * m[3] + 3.0 * U * U * m[1] - U * U * U * m[0];
+    double mu12 = m[8] - 2.0 * V * m[4] + V * V * m[1] - U * (m[5] - 2.0 * V * m[2] + V * V * m[0]);
+    double mu21 = m[7] - 2.0 * U * m[4] + U * U * m[2] - V * (m[3] - 2.0 * U * m[1] + U * U * m[0]);
+    double mu03 = m[9] - 3.0 * V * m[5] + 3.0 * V * V * m[2] - V * V * V * m[0];
+    q[0] = 0.5 * (mu30 + mu12 + mb[1] - U * mb[0]);
+    q[1] = 0.5 * (mu21 + mu03 + mb[2] - V * mb[0]);
+}
+
+// local pseudo step of cell c from its W at all levels (Eqs. 31-32)
+__device__ inline double local_dt(const Params &P, const double *Wc, int i, int j)
+{
+    if (P.dt_mode == 1) return P.dt_fixed;
+    double nu = 0.0;
+    for (int n = 0; n < P.NT; n++) {
+        double p[4];
+        prim4(P.K, Wc + n * 4, p);
+        const double cs = sqrt(P.gamma / (2.0 * p[3]));
+        const double ut = fmax(P.umax, fabs(p[1])) + cs, vt = fmax(P.umax, fabs(p[2])) + cs;
+        nu = fmax(nu, ut * P.rdx[i] + vt * P.rdy[j]);
+    }
+    return P.cfl / (nu + P.omega * P.NH);
+}
+
+__device__ inline void cell_eq(const Params &P, const double *Wc, const double *cm, double *out)
+{
+    double p[4], q[2];
+    prim4(P.K, Wc, p);
+    heat_flux_raw(cm, cm + 10, p[1], p[2], q);
+    const double s = (1.0 - P.Pr) * 4.0 * p[3] * p[3] / (5.0 * p[0]);
+    out[0] = p[3];
+    out[1] = p[1];
+    out[2] = p[2];
+    out[3] = p[0] * p[3] / HB_PI;
+    out[4] = 1.0 / tau_of(P, p[0], p[3]);
+    out[5] = s * q[0];
+    out[6] = s * q[1];
+}
+
+// one thread per cell: macro update (Eq. 29), collision records, residual terms, next local step
+__global__ __launch_bounds__(128) void k_cells(Params P, const double *__restrict__ feed, const double *__restrict__ recx,
+                                               const double *__restrict__ recy, const double *__restrict__ Wk,
+                                               const double *__restrict__ dtc, double *__restrict__ Wn,
+                                               double *__restrict__ crec, double *__restrict__ dtn,
+                                               double *__restrict__ rpart)
+{
+    __shared__ double red[4][128];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2[4] = {0, 0, 0, 0};
+    if (c < P.nc) {
+        const int NT = P.NT, nx = P.nx, i = c % nx, j = c / nx;
+        const double dG = dtc[c];
+        const double *Wc = Wk + (long)c * NT * 4;
+        double *Wo = Wn + (long)c * NT * 4;
+        for (int n = 0; n < NT; n++) {
+            const double *Fw = recx + ((long)(j * (nx + 1) + i) * NT + n) * REC;
+            const double *Fe = recx + ((long)(j * (nx + 1) + i + 1) * NT + n) * REC;
+            const double *Fs = recy + ((long)(j * nx + i) * NT + n) * REC;
+            const double *Fn = recy + ((long)((j + 1) * nx + i) * NT + n) * REC;
+            for (int k = 0; k < 4; k++) {
+                double src = 0.0;
+                for (int mm = 0; mm < NT; mm++) src += P.E[n * NT + mm] * Wc[mm * 4 + k];
+                const double div = (Fe[k] - Fw[k]) * P.rdx[i] + (Fn[k] - Fs[k]) * P.rdy[j];
+                Wo[n * 4 + k] = Wc[n * 4 + k] - dG * (div + P.omega * src);
+            }
+            const double *cm = feed + ((long)c * NT + n) * FEED + FEED_CM;
+            double *cr = crec + ((long)c * NT + n) * CREC;
+            cell_eq(P, Wc + n * 4, cm, cr);
+            cell_eq(P, Wo + n * 4, cm, cr + 7);
+        }
+        for (int k = 0; k < 4; k++) {
+            const double d = Wo[k] - Wc[k];
+            d2[k] = d * d;
+        }
+        dtn[c] = local_dt(P, Wo, i, j);
+    }
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = d2[k];
+    __syncthreads();
+    for (int s = 64; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) rpart[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------- K4: residual
+__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
+                                               int slot, int *__restrict__ flag)
+{
+    __shared__ double red[4][256];
+    double s[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int k = 0; k < 4; k++) s[k] += rpart[b * 4 + k];
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        const double r = sqrt(red[threadIdx.x][0] / nc);
+        ring[slot * 4 + threadIdx.x] = r;
+        if (!isfinite(r)) atomicOr(flag, 1);
+    }
+}
+
+// ---------------------------------------------------------------- K5: update
+// One block per cell.  LDS holds the 1-D Maxwellian factor tables of the four
+// faces (merged normal table + one tangential table per upwind side) and of
+// the cell equilibria at k and k+1, for every level.
+struct Lane {
+    double u, v;
+    int iu, iv;
+};
+
+__device__ inline double p3_eval(const double *c, double n, double t)
+{
+    return c[0] + n * (c[1] + n * (c[3] + n * c[6]) + t * (c[4] + n * c[7])) + t * (c[2] + t * (c[5] + t * c[9] + n * c[8]));
+}
+
+// micro flux through one face for this lane: u_n (e Q(n,t) + c4 f0 + c5 s)
+__device__ inline void face_flux(const double *__restrict__ rec, int side, const double *__restrict__ tn,
+                                 const double *__restrict__ tt, int in_, int it_, double un, double ut, double h0,
+                                 double b0, double sh, double sb, double &Hh, double &Hb)
+{
+    const double *s = rec + REC_SIDE + REC_SIDEW * side;
+    const double e = tn[in_] * tt[it_];
+    const double qh = p3_eval(s + 3, un, ut), qb = p3_eval(s + 13, un, ut);
+    Hh = un * (e * qh + s[23] * h0 + s[24] * sh);
+    Hb = un * (e * qb + s[23] * b0 + s[24] * sb);
+}
+
+__global__ __launch_bounds__(256) void k_update(Params P, const double *__restrict__ h, const double *__restrict__ b,
+                                                const double *__restrict__ recx, const double *__restrict__ recy,
+                                                const double *__restrict__ crec, const double *__restrict__ dtc,
+                                                double *__restrict__ hn, double *__restrict__ bn)
+{
+    extern __shared__ double tab[];
+    const int c = xcd_cell(blockIdx.x, gridDim.x);
+    const int NT = P.NT, M = P.M, nx = P.nx, ny = P.ny, K = P.K;
+    const int i = c % nx, j = c / nx;
+    // face record pointers: 0 west, 1 east, 2 south, 3 north
+    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
+                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
+    const double *cr = crec + (long)c * NT * CREC;
+    // tables
+    const int ftab = 12 * NT * M;
+    for (int t = threadIdx.x; t < 16 * NT * M; t += blockDim.x) {
+        const int k = t % M;
+        const double x = P.u1[k];
+        double lam, U;
+        if (t < ftab) {
+            const int which = (t / M) % 3, fn = t / (3 * M), n = fn % NT, fs = fn / NT;
+            const double *rec = fr[fs] + n * REC;
+            if (which == 0) {
+                const double *s = rec + REC_SIDE + REC_SIDEW * (x > 0.0 ? 1 : 0);
+                lam = s[0];
+                U = s[1];
+            } else {
+                const double *s = rec + REC_SIDE + REC_SIDEW * (which - 1);
+                lam = s[0];
+                U = s[2];
+            }
+        } else {
+            const int tt = t - ftab, which = (tt / M) % 4, n = tt / (4 * M);
+            const double *cc = cr + n * CREC + (which >= 2 ? 7 : 0);
+            lam = cc[0];
+            U = (which & 1) ? cc[2] : cc[1];
+        }
+        tab[t] = exp(-lam * (x - U) * (x - U));
+    }
+    __syncthreads();
+    const double *ctab = tab + ftab;
+    const long sx = (long)NT * P.nvp, sy = (long)nx * NT * P.nvp;
+    const double dG = dtc[c];
+    const double om = P.omega;
+
+    for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
+        const int r = ap % P.Qp;
+        if (r >= P.Q) continue;
+        const double u = P.vu[ap], v = P.vv[ap];
+        const int iu = P.viu[ap], iv = P.viv[ap];
+        const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
+        const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
+        double hk[HB_NTMAX], bk[HB_NTMAX], dh[HB_NTMAX], db[HB_NTMAX];
+        for (int n = 0; n < NT; n++) {
+            const long e = ((long)c * NT + n) * P.nvp + ap;
+            const double hc = h[e], bc = b[e];
+            hk[n] = hc;
+            bk[n] = bc;
+            const double sxh = line_slope(h + e - i * sx, sx, i, nx, hc, P.rcx);
+            const double sxb = line_slope(b + e - i * sx, sx, i, nx, bc, P.rcx);
+            const double syh = line_slope(h + e - j * sy, sy, j, ny, hc, P.rcy);
+            const double syb = line_slope(b + e - j * sy, sy, j, ny, bc, P.rcy);
+            const double sh = u * sxh + v * syh, sb = u * sxb + v * syb;
+            double Hx_out, Bx_out, Hx_in, Bx_in, Hy_out, By_out, Hy_in, By_in;
+            // ---- x faces (normal u, tangential v)
+            {
+                const int fo = su ? 1 : 0, fi_ = su ? 0 : 1;
+                const double xfo = su ? P.xf[i + 1] : P.xf[i];
+                const double *tbo = tab + (fo * NT + n) * 3 * M;
+                face_flux(fr[fo] + n * REC, su, tbo, tbo + (1 + su) * M, iu, iv, u, v, hc + sxh * (xfo - P.xc[i]),
+                          bc + sxb * (xfo - P.xc[i]), sh, sb, Hx_out, Bx_out);
+                const double *tbi = tab + (fi_ * NT + n) * 3 * M;
+                const bool wall = su ? (i == 0) : (i == nx - 1);
+                if (wall) {
+                    face_flux(fr[fi_] + n * REC, su, tbi, tbi + (1 + su) * M, iu, iv, u, v, 0.0, 0.0, 0.0, 0.0, Hx_in,
+                              Bx_in);
+                } else {
+                    const int iU = su ? i - 1 : i + 1;
+                    const long eU = e + (su ? -sx : sx);
+                    const double hU = h[eU], bU = b[eU];
+                    const double sxhU = line_slope(h + eU - iU * sx, sx, iU, nx, hU, P.rcx);
+                    const double sxbU = line_slope(b + eU - iU * sx, sx, iU, nx, bU, P.rcx);
+                    const double syhU = line_slope(h + eU - j * sy, sy, j, ny, hU, P.rcy);
+                    const double sybU = line_slope(b + eU - j * sy, sy, j, ny, bU, P.rcy);
+                    const double xfi = su ? P.xf[i] : P.xf[i + 1];
+                    face_flux(fr[fi_] + n * REC, su, tbi, tbi + (1 + su) * M, iu, iv, u, v,
+                              hU + sxhU * (xfi - P.xc[iU]), bU + sxbU * (xfi - P.xc[iU]), u * sxhU + v * syhU,
+                              u * sxbU + v * sybU, Hx_in, Bx_in);
+                }
+            }
+            // ---- y faces (normal v, tangential u)
+            {
+                const int fo = sv ? 3 : 2, fi_ = sv ? 2 : 3;
+                const double yfo = sv ? P.yf[j + 1] : P.yf[j];
+                const double *tbo = tab + (fo * NT + n) * 3 * M;
+                face_flux(fr[fo] + n * REC, sv, tbo, tbo + (1 + sv) * M, iv, iu, v, u, hc + syh * (yfo - P.yc[j]),
+                          bc + syb * (yfo - P.yc[j]), sh, sb, Hy_out, By_out);
+                const double *tbi = tab + (fi_ * NT + n) * 3 * M;
+                const bool wall = sv ? (j == 0) : (j == ny - 1);
+                if (wall) {
+                    face_flux(fr[fi_] + n * REC, sv, tbi, tbi + (1 + sv) * M, iv, iu, v, u, 0.0, 0.0, 0.0, 0.0, Hy_in,
+                              By_in);
+                } else {
+                    const int jU = sv ? j - 1 : j + 1;
+                    const long eU = e + (sv ? -sy : sy);
+                    const double hU = h[eU], bU = b[eU];
+                    const double sxhU = line_slope(h + eU - i * sx, sx, i, nx, hU, P.rcx);
+                    const double sxbU = line_slope(b + eU - i * sx, sx, i, nx, bU, P.rcx);
+                    const double syhU = line_slope(h + eU - jU * sy, sy, jU, ny, hU, P.rcy);
+                    const double sybU = line_slope(b + eU - jU * sy, sy, jU, ny, bU, P.rcy);
+                    const double yfi = sv ? P.yf[j] : P.yf[j + 1];
+                    face_flux(fr[fi_] + n * REC, sv, tbi, tbi + (1 + sv) * M, iv, iu, v, u,
+                              hU + syhU * (yfi - P.yc[jU]), bU + sybU * (yfi - P.yc[jU]), u * sxhU + v * syhU,
+                              u * sxbU + v * sybU, Hy_in, By_in);
+                }
+            }
+            const double east_h = su ? Hx_out : Hx_in, west_h = su ? Hx_in : Hx_out;
+            const double east_b = su ? Bx_out : Bx_in, west_b = su ? Bx_in : Bx_out;
+            const double north_h = sv ? Hy_out : Hy_in, south_h = sv ? Hy_in : Hy_out;
+            const double north_b = sv ? By_out : By_in, south_b = sv ? By_in : By_out;
+            dh[n] = (east_h - west_h) * P.rdx[i] + (north_h - south_h) * P.rdy[j];
+            db[n] = (east_b - west_b) * P.rdx[i] + (north_b - south_b) * P.rdy[j];
+        }
+        // spectral source, semi-implicit collision (Eq. 30), write
+        for (int n = 0; n < NT; n++) {
+            double Eh = 0.0, Eb = 0.0;
+            for (int m = 0; m < NT; m++) {
+                Eh += P.E[n * NT + m] * hk[m];
+                Eb += P.E[n * NT + m] * bk[m];
+            }
+            const double *cc = cr + n * CREC;
+            const double *ct = ctab + n * 4 * M;
+            double heq[2], beq[2], itau[2];
+            for (int s = 0; s < 2; s++) {
+                const double *q = cc + 7 * s;
+                const double lam = q[0];
+                const double e = ct[(2 * s) * M + iu] * ct[(2 * s + 1) * M + iv] * q[3];
+                const double cu = u - q[1], cv = v - q[2];
+                const double c2 = cu * cu + cv * cv, cq = cu * q[5] + cv * q[6];
+                heq[s] = e * (1.0 + cq * (2.0 * lam * c2 + K - 5.0));
+                beq[s] = e * (K / (2.0 * lam)) * (1.0 + cq * (2.0 * lam * c2 + K - 3.0));
+                itau[s] = q[4];
+            }
+            const double den = 1.0 + 0.5 * dG * itau[1];
+            const double hnew = (hk[n] - dG * dh[n] - dG * om * Eh + 0.5 * dG * (heq[1] * itau[1] + (heq[0] - hk[n]) * itau[0])) / den;
+            const double bnew = (bk[n] - dG * db[n] - dG * om * Eb + 0.5 * dG * (beq[1] * itau[1] + (beq[0] - bk[n]) * itau[0])) / den;
+            const long e = ((long)c * NT + n) * P.nvp + ap;
+            hn[e] = hnew;
+            bn[e] = bnew;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- set-up kernels
+__global__ void k_init(Params P, double *h, double *b, double *W)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nel = (long)P.nc * P.NT * P.nvp;
+    if (t < nel) {
+        const int ap = t % P.nvp;
+        const bool valid = (ap % P.Qp) < P.Q;
+        const double u = P.vu[ap], v = P.vv[ap];
+        const double H = valid ? exp(-(u * u + v * v)) / HB_PI : 0.0;
+        h[t] = H;
+        b[t] = 0.5 * P.K * H;
+    }
+    if (t < (long)P.nc * P.NT) {
+        W[t * 4 + 0] = 1.0;
+        W[t * 4 + 1] = 0.0;
+        W[t * 4 + 2] = 0.0;
+        W[t * 4 + 3] = (2.0 + P.K) / 4.0;
+    }
+}
+
+__global__ void k_dt(Params P, const double *W, double *dtc)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < P.nc) dtc[c] = local_dt(P, W + (long)c * P.NT * 4, c % P.nx, c / P.nx);
+}
+
+// ---------------------------------------------------------------- harmonics
+// per (cell, level): rho, U, V, T/T0 from W; P_xy, q_x, q_y from h, b about U, V
+__global__ __launch_bounds__(256) void k_harm_vars(Params P, const double *__restrict__ h, const double *__restrict__ b,
+                                                   const double *__restrict__ W, double *__restrict__ vars)
+{
+    __shared__ double red[3][256];
+    const int c = blockIdx.x;
+    for (int n = 0; n < P.NT; n++) {
+        double p[4];
+        prim4(P.K, W + ((long)c * P.NT + n) * 4, p);
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
+            const long e = ((long)c * P.NT + n) * P.nvp + ap;
+            const double w = P.vw[ap], cu = P.vu[ap] - p[1], cv = P.vv[ap] - p[2];
+            const double hh = h[e], en = (cu * cu + cv * cv) * hh + b[e];
+            s0 += w * cu * cv * hh;
+            s1 += w * cu * en;
+            s2 += w * cv * en;
+        }
+        red[0][threadIdx.x] = s0;
+        red[1][threadIdx.x] = s1;
+        red[2][threadIdx.x] = s2;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s)
+                for (int k = 0; k < 3; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double *o = vars + ((long)c * P.NT + n) * 7;
+            o[0] = p[0];
+            o[1] = p[1];
+            o[2] = p[2];
+            o[3] = 1.0 / p[3];
+            o[4] = red[0][0];
+            o[5] = 0.5 * red[1][0];
+            o[6] = 0.5 * red[2][0];
+        }
+        __syncthreads();
+    }
+}
+
+// thread per (var, k, cell): qhat_k = (1/NT) sum_n q_n exp(-i k 2 pi n / NT)
+__global__ void k_harm_dft(Params P, const double *__restrict__ vars, double *__restrict__ re, double *__restrict__ im)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int NH = P.NH, NT = P.NT, nc = P.nc;
+    if (t >= (long)7 * (NH + 1) * nc) return;
+    const int c = t % nc, k = (t / nc) % (NH + 1), var = t / ((long)nc * (NH + 1));
+    double sr = 0.0, si = 0.0;
+    for (int n = 0; n < NT; n++) {
+        const double th = 2.0 * HB_PI * k * n / NT;
+        const double val = vars[((long)c * NT + n) * 7 + var];
+        sr += val * cos(th);
+        si -= val * sin(th);
+    }
+    re[t] = sr / NT;
+    im[t] = si / NT;
+}
+
+}  // namespace hb

@@ -1,0 +1,539 @@
+// Host runtime and C ABI of the HB-UGKS pseudo-step library (see hb_ugks.h).
+//
+// The handle owns the device state of one case: geometry and velocity
+// tables, the double-buffered (h, b), W and local steps, the per-step
+// moment/face/cell records and a residual ring buffer.  A pseudo step is
+// five kernel launches on the handle's stream (moments, faces, cells,
+// residual, update) followed by a buffer swap.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hb_ugks.h"
+#include "hb_kernels.h"
+
+namespace {
+
+constexpr int RING = 1024;
+constexpr int NKERN = 5;
+const char *KNAMES[NKERN] = {"moments", "faces", "cells", "residual", "update"};
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct hb_ugks {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = HB_FP64;
+    size_t budget = 0;
+    size_t bytes = 0;
+    bool has_case = false;
+    hb::Params P{};
+    // device buffers
+    std::vector<Buf> bufs;
+    double *geo = nullptr;  // xf, yf, xc, yc, rdx, rdy, rcx, rcy, u1, w1
+    double *vel = nullptr;  // vu, vv, vw
+    int *veli = nullptr;    // viu, viv
+    double *h[2]{}, *b[2]{}, *W[2]{}, *dt[2]{};
+    double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
+    int *flag = nullptr;
+    int cur = 0;
+    long step = 0;
+    int cells_blocks = 0;
+    size_t upd_lds = 0;
+    std::vector<int> perm;  // natural alpha -> internal alpha'
+    // timing
+    bool timing = false;
+    hipEvent_t ev[NKERN + 1]{};
+    double kms[NKERN]{};
+    long klaunch[NKERN]{};
+};
+
+#define HIPOK(x)                                    \
+    do {                                            \
+        if ((x) != hipSuccess) return HB_EDEVICE;   \
+    } while (0)
+
+static void free_case(hb_ugks *H)
+{
+    for (auto &b : H->bufs) (void)hipFree(b.p);
+    H->bufs.clear();
+    H->bytes = 0;
+    H->has_case = false;
+}
+
+static int dalloc(hb_ugks *H, void **p, size_t nbytes)
+{
+    if (H->budget && H->bytes + nbytes > H->budget) return HB_ENOMEM;
+    if (hipMalloc(p, nbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return HB_ENOMEM;
+    }
+    H->bufs.push_back({*p, nbytes});
+    H->bytes += nbytes;
+    return HB_OK;
+}
+
+extern "C" {
+
+void hb_ugks_default_numerics(hb_numerics *o)
+{
+    if (!o) return;
+    o->cfl = 0.5;
+    o->face_dt = 0;
+    o->Pr = 2.0 / 3.0;
+    o->omega_vss = 0.81;
+    o->alpha_vss = 1.0;
+    o->K_int = 1;
+    o->dt_mode = 0;
+    o->dt_fixed = 0.0;
+}
+
+const char *hb_ugks_strerror(int s)
+{
+    switch (s) {
+    case HB_OK: return "ok";
+    case HB_EINVAL: return "invalid argument";
+    case HB_ENOMEM: return "device memory exhausted or over budget";
+    case HB_ESTATE: return "call out of order (no case set)";
+    case HB_EDIVERGED: return "non-finite residual: the iteration diverged";
+    case HB_EDEVICE: return "HIP runtime error or no gfx950 device";
+    case HB_ECAPACITY: return "output buffer too small";
+    default: return "unknown status";
+    }
+}
+
+int hb_ugks_create(const hb_create_opts *opts, hb_handle *out)
+{
+    if (!out) return HB_EINVAL;
+    *out = nullptr;
+    hb_create_opts o{0, nullptr, HB_FP64, 0};
+    if (opts) o = *opts;
+    if (o.precision != HB_FP64) return HB_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
+        (void)hipGetLastError();
+        return HB_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o.device) != hipSuccess) return HB_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HB_EDEVICE;
+    hb_ugks *H = new (std::nothrow) hb_ugks();
+    if (!H) return HB_ENOMEM;
+    H->device = o.device;
+    H->stream = (hipStream_t)o.stream;
+    H->precision = o.precision;
+    H->budget = o.hbm_budget_bytes;
+    *out = H;
+    return HB_OK;
+}
+
+void hb_ugks_destroy(hb_handle H)
+{
+    if (!H) return;
+    (void)hipSetDevice(H->device);
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    else (void)hipDeviceSynchronize();
+    free_case(H);
+    for (auto &e : H->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete H;
+}
+
+int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, int NH, const hb_wall walls[4],
+                     const hb_vgrid *vg, const hb_numerics *num)
+{
+    if (!H || !g || !walls || !vg) return HB_EINVAL;
+    hb_numerics nm;
+    hb_ugks_default_numerics(&nm);
+    if (num) nm = *num;
+    const int nx = g->nx, ny = g->ny, M = vg->m;
+    if (nx < 3 || ny < 3 || M < 4 || M > 128 || (M & 1) || NH < 0 || 2 * NH + 1 > HB_NTMAX || !(Kn > 0.0) ||
+        !(St >= 0.0) || !(vg->umax > 0.0) || !(nm.cfl > 0.0) || nm.K_int < 0 || !(nm.Pr > 0.0) ||
+        (nm.dt_mode == 1 && !(nm.dt_fixed > 0.0)) || !(g->L > 0.0) || !(g->H > 0.0))
+        return HB_EINVAL;
+    for (int w = 0; w < 4; w++)
+        if (!(walls[w].T_mean - std::hypot(walls[w].T_hat_re, walls[w].T_hat_im) > 0.0)) return HB_EINVAL;
+    std::vector<double> xf(nx + 1), yf(ny + 1);
+    for (int i = 0; i <= nx; i++) xf[i] = g->x_faces ? g->x_faces[i] : g->L * i / nx;
+    for (int j = 0; j <= ny; j++) yf[j] = g->y_faces ? g->y_faces[j] : g->H * j / ny;
+    for (int i = 0; i < nx; i++)
+        if (!(xf[i + 1] > xf[i])) return HB_EINVAL;
+    for (int j = 0; j < ny; j++)
+        if (!(yf[j + 1] > yf[j])) return HB_EINVAL;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    free_case(H);
+
+    hb::Params &P = H->P;
+    P = hb::Params{};
+    P.nx = nx;
+    P.ny = ny;
+    P.nc = nx * ny;
+    P.M = M;
+    P.Mh = M / 2;
+    P.Q = P.Mh * P.Mh;
+    P.Qp = (P.Q + 63) / 64 * 64;
+    P.nvp = 4 * P.Qp;
+    P.NH = NH;
+    P.NT = 2 * NH + 1;
+    P.K = nm.K_int;
+    P.face_dt = nm.face_dt;
+    P.dt_mode = nm.dt_mode;
+    P.dt_fixed = nm.dt_fixed;
+    P.omega = St;  // Eq. (37) with H = sqrt(2 R T0) = 1
+    {
+        const double a = nm.alpha_vss, w = nm.omega_vss;
+        const double coef = 4.0 * a * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) / (5.0 * (a + 1.0) * (a + 2.0));
+        P.mu_ref = Kn * std::sqrt(M_PI) / coef;  // Eq. (36), rho0 = H = 1, sqrt(2 pi R T0) = sqrt(pi)
+    }
+    P.omega_vss = nm.omega_vss;
+    P.Pr = nm.Pr;
+    P.cfl = nm.cfl;
+    P.gamma = (P.K + 4.0) / (P.K + 2.0);
+    P.umax = vg->umax;
+    const int NT = P.NT;
+    for (int n = 0; n < NT; n++)
+        for (int m = 0; m < NT; m++) {
+            const int d = n - m;
+            P.E[n * NT + m] = d == 0 ? 0.0 : 0.5 * ((d % 2 == 0) ? 1.0 : -1.0) / std::sin(M_PI * d / NT);  // Eq. (17)
+        }
+    for (int w = 0; w < 4; w++)
+        for (int n = 0; n < NT; n++) {
+            const double th = 2.0 * M_PI * n / NT;  // omega t_n, Eq. (12)
+            P.wall_ut[w][n] = walls[w].ut_mean + walls[w].ut_hat_re * std::cos(th) - walls[w].ut_hat_im * std::sin(th);
+            P.wall_T[w][n] = walls[w].T_mean + walls[w].T_hat_re * std::cos(th) - walls[w].T_hat_im * std::sin(th);
+        }
+
+    // host tables
+    std::vector<double> geo;
+    geo.insert(geo.end(), xf.begin(), xf.end());
+    geo.insert(geo.end(), yf.begin(), yf.end());
+    std::vector<double> xc(nx), yc(ny), rdx(nx), rdy(ny), rcx(nx, 0.0), rcy(ny, 0.0), u1(M), w1(M);
+    for (int i = 0; i < nx; i++) {
+        xc[i] = 0.5 * (xf[i] + xf[i + 1]);
+        rdx[i] = 1.0 / (xf[i + 1] - xf[i]);
+    }
+    for (int j = 0; j < ny; j++) {
+        yc[j] = 0.5 * (yf[j] + yf[j + 1]);
+        rdy[j] = 1.0 / (yf[j + 1] - yf[j]);
+    }
+    for (int i = 1; i < nx; i++) rcx[i] = 1.0 / (xc[i] - xc[i - 1]);
+    for (int j = 1; j < ny; j++) rcy[j] = 1.0 / (yc[j] - yc[j - 1]);
+    const double du = 2.0 * vg->umax / (M - 1);
+    for (int k = 0; k < M; k++) {
+        u1[k] = -vg->umax + k * du;
+        w1[k] = (k == 0 || k == M - 1) ? 0.5 * du : du;
+    }
+    const size_t ox_xc = geo.size();
+    geo.insert(geo.end(), xc.begin(), xc.end());
+    const size_t ox_yc = geo.size();
+    geo.insert(geo.end(), yc.begin(), yc.end());
+    const size_t ox_rdx = geo.size();
+    geo.insert(geo.end(), rdx.begin(), rdx.end());
+    const size_t ox_rdy = geo.size();
+    geo.insert(geo.end(), rdy.begin(), rdy.end());
+    const size_t ox_rcx = geo.size();
+    geo.insert(geo.end(), rcx.begin(), rcx.end());
+    const size_t ox_rcy = geo.size();
+    geo.insert(geo.end(), rcy.begin(), rcy.end());
+    const size_t ox_u1 = geo.size();
+    geo.insert(geo.end(), u1.begin(), u1.end());
+    const size_t ox_w1 = geo.size();
+    geo.insert(geo.end(), w1.begin(), w1.end());
+
+    // internal velocity order: quadrant q = (u>0) + 2 (v>0), then (iv, iu) inside it, 64-padded
+    const int Mh = P.Mh, Qp = P.Qp, nvp = P.nvp;
+    std::vector<double> vel(3 * (size_t)nvp, 0.0);
+    std::vector<int> veli(2 * (size_t)nvp, 0);
+    H->perm.assign((size_t)M * M, -1);
+    for (int q = 0; q < 4; q++)
+        for (int r = 0; r < Qp; r++) {
+            const int rr = r < P.Q ? r : 0;  // padding repeats the first velocity with zero weight
+            const int il = rr % Mh, jl = rr / Mh;
+            const int iu = (q & 1) ? Mh + il : il, iv = (q & 2) ? Mh + jl : jl;
+            const int ap = q * Qp + r;
+            vel[ap] = u1[iu];
+            vel[nvp + ap] = u1[iv];
+            vel[2 * (size_t)nvp + ap] = r < P.Q ? w1[iu] * w1[iv] : 0.0;
+            veli[ap] = iu;
+            veli[nvp + ap] = iv;
+            if (r < P.Q) H->perm[(size_t)iv * M + iu] = ap;
+        }
+
+    const size_t nel = (size_t)P.nc * NT * nvp;
+    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
+    H->cells_blocks = (P.nc + 127) / 128;
+    int rc = HB_OK;
+#define ALLOC(ptr, count, T)                                            \
+    do {                                                                \
+        rc = dalloc(H, (void **)&(ptr), sizeof(T) * (size_t)(count));  \
+        if (rc != HB_OK) {                                              \
+            free_case(H);                                               \
+            return rc;                                                  \
+        }                                                               \
+    } while (0)
+    ALLOC(H->geo, geo.size(), double);
+    ALLOC(H->vel, vel.size(), double);
+    ALLOC(H->veli, veli.size(), int);
+    for (int s = 0; s < 2; s++) {
+        ALLOC(H->h[s], nel, double);
+        ALLOC(H->b[s], nel, double);
+        ALLOC(H->W[s], (size_t)P.nc * NT * 4, double);
+        ALLOC(H->dt[s], P.nc, double);
+    }
+    ALLOC(H->feed, (size_t)P.nc * NT * hb::FEED, double);
+    ALLOC(H->recx, nfx * NT * hb::REC, double);
+    ALLOC(H->recy, nfy * NT * hb::REC, double);
+    ALLOC(H->crec, (size_t)P.nc * NT * hb::CREC, double);
+    ALLOC(H->rpart, (size_t)H->cells_blocks * 4, double);
+    ALLOC(H->ring, (size_t)RING * 4, double);
+    ALLOC(H->flag, 1, int);
+#undef ALLOC
+    HIPOK(hipMemcpy(H->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(H->vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(H->veli, veli.data(), veli.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPOK(hipMemset(H->flag, 0, sizeof(int)));
+    HIPOK(hipMemset(H->ring, 0, sizeof(double) * RING * 4));
+    P.xf = H->geo;
+    P.yf = H->geo + (nx + 1);
+    P.xc = H->geo + ox_xc;
+    P.yc = H->geo + ox_yc;
+    P.rdx = H->geo + ox_rdx;
+    P.rdy = H->geo + ox_rdy;
+    P.rcx = H->geo + ox_rcx;
+    P.rcy = H->geo + ox_rcy;
+    P.u1 = H->geo + ox_u1;
+    P.w1 = H->geo + ox_w1;
+    P.vu = H->vel;
+    P.vv = H->vel + nvp;
+    P.vw = H->vel + 2 * (size_t)nvp;
+    P.viu = H->veli;
+    P.viv = H->veli + nvp;
+    H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
+    if (H->upd_lds > 160 * 1024) {
+        free_case(H);
+        return HB_EINVAL;
+    }
+    if (H->upd_lds > 64 * 1024)
+        HIPOK(hipFuncSetAttribute((const void *)hb::k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)H->upd_lds));
+    H->cur = 0;
+    H->step = 0;
+    const long tot = (long)nel;
+    hipLaunchKernelGGL(hb::k_init, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P, H->h[0], H->b[0], H->W[0]);
+    hipLaunchKernelGGL(hb::k_init, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P, H->h[1], H->b[1], H->W[1]);
+    hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[0], H->dt[0]);
+    HIPOK(hipGetLastError());
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    H->has_case = true;
+    return HB_OK;
+}
+
+int hb_ugks_pseudo_step(hb_handle H, int nsteps)
+{
+    if (!H) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    if (nsteps < 0) return HB_EINVAL;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    const hb::Params &P = H->P;
+    const int NT = P.NT;
+    const int nfaces = (P.nx + 1) * P.ny + P.nx * (P.ny + 1);
+    for (int s = 0; s < nsteps; s++) {
+        const int c = H->cur, x = 1 - c;
+        const int slot = (int)(H->step % RING);
+        if (H->timing) HIPOK(hipEventRecord(H->ev[0], H->stream));
+        hipLaunchKernelGGL(hb::k_moments, dim3(P.nc), dim3(256), 0, H->stream, P, H->h[c], H->b[c], H->feed);
+        if (H->timing) HIPOK(hipEventRecord(H->ev[1], H->stream));
+        hipLaunchKernelGGL(hb::k_faces, dim3((nfaces * NT + 127) / 128), dim3(128), 0, H->stream, P, H->feed, H->W[c],
+                           H->dt[c], H->recx, H->recy);
+        if (H->timing) HIPOK(hipEventRecord(H->ev[2], H->stream));
+        hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
+                           H->W[c], H->dt[c], H->W[x], H->crec, H->dt[x], H->rpart);
+        if (H->timing) HIPOK(hipEventRecord(H->ev[3], H->stream));
+        hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
+                           slot, H->flag);
+        if (H->timing) HIPOK(hipEventRecord(H->ev[4], H->stream));
+        hipLaunchKernelGGL(hb::k_update, dim3(P.nc), dim3(256), H->upd_lds, H->stream, P, H->h[c], H->b[c], H->recx,
+                           H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+        if (H->timing) {
+            HIPOK(hipEventRecord(H->ev[5], H->stream));
+            HIPOK(hipEventSynchronize(H->ev[5]));
+            for (int k = 0; k < NKERN; k++) {
+                float ms = 0.f;
+                HIPOK(hipEventElapsedTime(&ms, H->ev[k], H->ev[k + 1]));
+                H->kms[k] += ms;
+                H->klaunch[k]++;
+            }
+        }
+        HIPOK(hipGetLastError());
+        H->cur = x;
+        H->step++;
+    }
+    return HB_OK;
+}
+
+int hb_ugks_residual(hb_handle H, double out[4], long *step_index)
+{
+    if (!H || !out) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    if (step_index) *step_index = H->step;
+    if (H->step == 0) {
+        for (int k = 0; k < 4; k++) out[k] = 0.0;
+        return HB_OK;
+    }
+    const int slot = (int)((H->step - 1) % RING);
+    HIPOK(hipMemcpy(out, H->ring + slot * 4, 4 * sizeof(double), hipMemcpyDeviceToHost));
+    int flag = 0;
+    HIPOK(hipMemcpy(&flag, H->flag, sizeof(int), hipMemcpyDeviceToHost));
+    return flag ? HB_EDIVERGED : HB_OK;
+}
+
+int hb_ugks_sizes(hb_handle H, int out[6])
+{
+    if (!H || !out) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    out[0] = H->P.nx;
+    out[1] = H->P.ny;
+    out[2] = H->P.nc;
+    out[3] = H->P.M;
+    out[4] = H->P.M * H->P.M;
+    out[5] = H->P.NT;
+    return HB_OK;
+}
+
+size_t hb_ugks_device_bytes(hb_handle H) { return H ? H->bytes : 0; }
+
+int hb_ugks_state_out(hb_handle H, double *W, double *hh, double *bb, size_t capacity)
+{
+    if (!H) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    const hb::Params &P = H->P;
+    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.M;
+    if ((hh || bb) && capacity < ncn * nv) return HB_ECAPACITY;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    if (W) HIPOK(hipMemcpy(W, H->W[H->cur], ncn * 4 * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> tmp;
+    double *src[2] = {H->h[H->cur], H->b[H->cur]};
+    double *dst[2] = {hh, bb};
+    for (int s = 0; s < 2; s++) {
+        if (!dst[s]) continue;
+        tmp.resize(ncn * P.nvp);
+        HIPOK(hipMemcpy(tmp.data(), src[s], tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < ncn; e++)
+            for (size_t a = 0; a < nv; a++) dst[s][e * nv + a] = tmp[e * P.nvp + H->perm[a]];
+    }
+    return HB_OK;
+}
+
+int hb_ugks_state_in(hb_handle H, const double *W, const double *hh, const double *bb)
+{
+    if (!H) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    const hb::Params &P = H->P;
+    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.M;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    if (W) HIPOK(hipMemcpy(H->W[H->cur], W, ncn * 4 * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> tmp;
+    double *dst[2] = {H->h[H->cur], H->b[H->cur]};
+    const double *src[2] = {hh, bb};
+    for (int s = 0; s < 2; s++) {
+        if (!src[s]) continue;
+        tmp.assign(ncn * P.nvp, 0.0);
+        for (size_t e = 0; e < ncn; e++)
+            for (size_t a = 0; a < nv; a++) tmp[e * P.nvp + H->perm[a]] = src[s][e * nv + a];
+        HIPOK(hipMemcpy(dst[s], tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (W) {
+        hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[H->cur], H->dt[H->cur]);
+        HIPOK(hipGetLastError());
+        HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    }
+    return HB_OK;
+}
+
+int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im, size_t capacity)
+{
+    if (!H || !re || !im || (var_mask & ~0x7Fu) || !var_mask) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    const hb::Params &P = H->P;
+    int nsel = 0;
+    for (int v = 0; v < 7; v++) nsel += (var_mask >> v) & 1;
+    const size_t per = (size_t)(P.NH + 1) * P.nc;
+    if (capacity < nsel * per) return HB_ECAPACITY;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    double *vars = nullptr, *dre = nullptr, *dim_ = nullptr;
+    const size_t nvars = (size_t)P.nc * P.NT * 7, nout = 7 * per;
+    if (hipMalloc(&vars, nvars * sizeof(double)) != hipSuccess) return HB_ENOMEM;
+    if (hipMalloc(&dre, nout * sizeof(double)) != hipSuccess || hipMalloc(&dim_, nout * sizeof(double)) != hipSuccess) {
+        (void)hipFree(vars);
+        (void)hipFree(dre);
+        return HB_ENOMEM;
+    }
+    const int c = H->cur;
+    hipLaunchKernelGGL(hb::k_harm_vars, dim3(P.nc), dim3(256), 0, H->stream, P, H->h[c], H->b[c], H->W[c], vars);
+    hipLaunchKernelGGL(hb::k_harm_dft, dim3((nout + 255) / 256), dim3(256), 0, H->stream, P, vars, dre, dim_);
+    int rc = HB_OK;
+    if (hipGetLastError() != hipSuccess) rc = HB_EDEVICE;
+    std::vector<double> hre(nout), him(nout);
+    if (rc == HB_OK && (H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize()) != hipSuccess)
+        rc = HB_EDEVICE;
+    if (rc == HB_OK && hipMemcpy(hre.data(), dre, nout * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = HB_EDEVICE;
+    if (rc == HB_OK && hipMemcpy(him.data(), dim_, nout * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = HB_EDEVICE;
+    (void)hipFree(vars);
+    (void)hipFree(dre);
+    (void)hipFree(dim_);
+    if (rc != HB_OK) return rc;
+    size_t o = 0;
+    for (int v = 0; v < 7; v++) {
+        if (!((var_mask >> v) & 1)) continue;
+        std::memcpy(re + o, hre.data() + v * per, per * sizeof(double));
+        std::memcpy(im + o, him.data() + v * per, per * sizeof(double));
+        o += per;
+    }
+    return HB_OK;
+}
+
+int hb_ugks_enable_timing(hb_handle H, int on)
+{
+    if (!H) return HB_EINVAL;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    if (on && !H->ev[0])
+        for (auto &e : H->ev) HIPOK(hipEventCreate(&e));
+    H->timing = on != 0;
+    for (int k = 0; k < NKERN; k++) {
+        H->kms[k] = 0.0;
+        H->klaunch[k] = 0;
+    }
+    return HB_OK;
+}
+
+int hb_ugks_kernel_times(hb_handle H, const char **names, long *launches, double *ms, int capacity)
+{
+    if (!H) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    if (capacity < NKERN) return HB_ECAPACITY;
+    for (int k = 0; k < NKERN; k++) {
+        if (names) names[k] = KNAMES[k];
+        if (launches) launches[k] = H->klaunch[k];
+        if (ms) ms[k] = H->kms[k];
+    }
+    return NKERN;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, and its host-side error paths behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2605_03479_amd as hb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hb_ugks.h")).read()
+    return sorted(set(re.findall(r"\b(hb_ugks_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_03479_amd import build as b
+    if b.stale():
+        b.build()
+    return hb.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(hb.EXPORTS)
+
+
+def test_strerror_and_defaults(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.hb_ugks_strerror(code)
+    assert b"unknown" in lib.hb_ugks_strerror(-99)
+    n = hb.default_numerics()
+    assert n.cfl == 0.5 and n.face_dt == 0 and abs(n.Pr - 2 / 3) < 1e-15 and n.K_int == 1
+
+
+def test_null_and_state_errors(lib):
+    assert lib.hb_ugks_create(None, None) == hb.HB_EINVAL
+    assert lib.hb_ugks_pseudo_step(None, 1) == hb.HB_EINVAL
+    assert lib.hb_ugks_set_case(None, None, 1.0, 1.0, 1, None, None, None) == hb.HB_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lib.hb_ugks_residual(None, out, None) == hb.HB_EINVAL
+    lib.hb_ugks_destroy(None)  # no-op
+
+
+def test_create_bad_precision_or_device(lib):
+    o = hb.hb_create_opts(0, None, 7, 0)
+    h = ctypes.c_void_p()
+    assert lib.hb_ugks_create(ctypes.byref(o), ctypes.byref(h)) == hb.HB_EINVAL
+    o = hb.hb_create_opts(4096, None, 0, 0)
+    assert lib.hb_ugks_create(ctypes.byref(o), ctypes.byref(h)) == hb.HB_EDEVICE
