@@ -1,0 +1,136 @@
+"""Benchmark: HB-UGKS pseudo steps per second on one MI355X.
+
+One step = one pass of the whole pseudo step (moments, faces, cells,
+residual, update) over the 64 x 64-cell, 32 x 32-velocity, NH = 1 shear
+cavity (Kn = 1, St = 1, lid 0.01 cos wt, Shakhov), FP64, state resident in
+HBM.  value = cell x velocity x level updates per second.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell·ξ·instance updates/s per pseudo-step (%HBM peak); cases/h; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kn", type=float, default=1.0)
+    ap.add_argument("--st", type=float, default=1.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(batched cases would shard by case with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import hbcases
+    import paper_2605_03479_amd as hb
+    from paper_2605_03479_amd import build as hb_build
+
+    if not os.path.exists(hb_build.LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    stream = None
+    sync = None
+    try:
+        import torch
+        if torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+            sync = torch.cuda.synchronize
+    except Exception:  # torch is plumbing only
+        pass
+
+    case = hbcases.shear_cavity(args.kn, args.st)
+    log(f"case {case.name}: {case.nc} cells x {case.nv} velocities x {case.NT} levels = {case.updates} updates/step")
+    s = hb.Solver(case, device=0, stream=stream)
+    s.step(args.warmup)
+    s.residual()  # synchronises the handle's stream
+    if sync:
+        sync()
+    s.enable_timing(True)
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    s.residual()
+    if sync:
+        sync()
+    t1 = time.perf_counter()
+    kt = s.kernel_times()
+    res = s.residual()
+    s.close()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ups = case.updates / (ms_step * 1e-3)
+    log(f"ms/step {ms_step:.4f}  updates/s {ups:.4e}  residual {res}")
+    for k, (n, ms) in kt.items():
+        log(f"  kernel {k:9s} launches {n:6d}  avg {ms / max(n, 1) * 1e3:9.2f} us")
+
+    # roofline of the dominant kernel: algorithmic HBM bytes per launch
+    #   update : read h, b and write h, b once per (cell, velocity, level) -> 4 x 8 B
+    #   moments: read h, b once -> 2 x 8 B
+    algo_bytes = {"update": 32.0 * case.updates, "moments": 16.0 * case.updates}
+    dom = max(kt, key=lambda k: kt[k][1])
+    n_dom, ms_dom = kt[dom]
+    avg_s = ms_dom / n_dom * 1e-3
+    if dom in algo_bytes:
+        achieved = algo_bytes[dom] / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo_bytes[dom]}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2)}
+    step_bytes = 48.0 * case.updates  # moments (2 words) + update (4 words) per update
+    kernels = {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt.items()}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(case)
+        o.step(1)  # first touch / page-in
+        steps = args.cpu_steps
+        if steps <= 0:
+            t = time.perf_counter()
+            o.step(1)
+            per = time.perf_counter() - t
+            steps = max(1, min(200, int(15.0 / max(per, 1e-6))))
+        t = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t
+        cpu = {"value": case.updates * steps / dt, "unit": "updates/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"{steps} pseudo steps of the same 64x64x32^2 NH=1 case ({dt:.1f} s)"}
+        log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": ups, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": case.name, "cells": case.nc, "velocities": case.nv, "levels": case.NT,
+                   "Kn": case.Kn, "St": case.St, "precision": "fp64"},
+        "effective_GBps_per_step": step_bytes / (ms_step * 1e-3) / 1e9,
+        "kernel_avg_us": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

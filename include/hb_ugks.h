@@ -138,11 +138,14 @@ int hb_ugks_sizes(hb_handle h, int out[6]);
 /* Device bytes held by the handle. */
 size_t hb_ugks_device_bytes(hb_handle h);
 
-/* Per-kernel timing: when enabled, every pseudo step records HIP events
- * around each of its kernels on the handle's stream; hb_ugks_kernel_times
- * synchronises and returns, per kernel of the step (in launch order), its
- * name, number of launches and summed milliseconds since timing was enabled.
- * Errors: HB_ESTATE, HB_ECAPACITY (fewer than the step's kernels). */
+/* Per-kernel timing: while enabled, every pseudo step records HIP events
+ * around each of its kernels on the handle's stream (no host synchronisation
+ * per step).  hb_ugks_kernel_times synchronises on the last event and fills,
+ * per kernel of the step in launch order, its name (static string), number of
+ * timed launches and summed milliseconds since timing was enabled; it returns
+ * the number of kernels (>= 0) or a negative HB_E* code.  Enabling (or
+ * disabling) resets the sums.
+ * Errors: HB_ESTATE, HB_ECAPACITY (capacity below the number of kernels). */
 int hb_ugks_enable_timing(hb_handle h, int on);
 int hb_ugks_kernel_times(hb_handle h, const char **names, long *launches, double *ms, int capacity);
 

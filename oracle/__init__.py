@@ -56,6 +56,7 @@ def lib():
         L.hbref_constants.argtypes = [ctypes.c_void_p, _D]
         L.hbref_max_nu.restype = ctypes.c_double
         L.hbref_max_nu.argtypes = [ctypes.c_void_p]
+        L.hbref_threads.restype = ctypes.c_int
         L.hbref_set_dt_scale.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.hbref_time.restype = ctypes.c_double
         L.hbref_time.argtypes = [ctypes.c_void_p]
@@ -73,6 +74,11 @@ def lib():
                                         _D, _D, _D, _D, _D]
         _LIB = L
     return _LIB
+
+
+def threads():
+    """OpenMP threads the oracle uses."""
+    return lib().hbref_threads()
 
 
 # ---------------------------------------------------------------- unit-level

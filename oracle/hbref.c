@@ -25,6 +25,7 @@
  * Everything is plain loops; OpenMP only splits independent rows/cells.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1194,6 +1195,9 @@ double hbref_max_nu(void *p)
     o->dt_mode = mode;
     return m;
 }
+
+/* OpenMP threads the oracle's parallel loops use. */
+int hbref_threads(void) { return omp_get_max_threads(); }
 
 /* Integer sizes of the handle: nx, ny, nc, M, nv, NT. */
 void hbref_sizes(void *p, int *out)

@@ -51,9 +51,10 @@ struct hb_ugks {
     int cells_blocks = 0;
     size_t upd_lds = 0;
     std::vector<int> perm;  // natural alpha -> internal alpha'
-    // timing
+    // timing: one set of NKERN + 1 events per timed step, read back lazily
     bool timing = false;
-    hipEvent_t ev[NKERN + 1]{};
+    std::vector<hipEvent_t> tev;
+    size_t tused = 0;
     double kms[NKERN]{};
     long klaunch[NKERN]{};
 };
@@ -144,8 +145,7 @@ void hb_ugks_destroy(hb_handle H)
     if (H->stream) (void)hipStreamSynchronize(H->stream);
     else (void)hipDeviceSynchronize();
     free_case(H);
-    for (auto &e : H->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &e : H->tev) (void)hipEventDestroy(e);
     delete H;
 }
 
@@ -351,34 +351,53 @@ int hb_ugks_pseudo_step(hb_handle H, int nsteps)
     for (int s = 0; s < nsteps; s++) {
         const int c = H->cur, x = 1 - c;
         const int slot = (int)(H->step % RING);
-        if (H->timing) HIPOK(hipEventRecord(H->ev[0], H->stream));
+        hipEvent_t *ev = nullptr;
+        if (H->timing) {
+            if (H->tused + NKERN + 1 > H->tev.size()) {
+                for (int k = 0; k <= NKERN; k++) {
+                    hipEvent_t e;
+                    HIPOK(hipEventCreate(&e));
+                    H->tev.push_back(e);
+                }
+            }
+            ev = H->tev.data() + H->tused;
+            H->tused += NKERN + 1;
+            HIPOK(hipEventRecord(ev[0], H->stream));
+        }
         hipLaunchKernelGGL(hb::k_moments, dim3(P.nc), dim3(256), 0, H->stream, P, H->h[c], H->b[c], H->feed);
-        if (H->timing) HIPOK(hipEventRecord(H->ev[1], H->stream));
+        if (ev) HIPOK(hipEventRecord(ev[1], H->stream));
         hipLaunchKernelGGL(hb::k_faces, dim3((nfaces * NT + 127) / 128), dim3(128), 0, H->stream, P, H->feed, H->W[c],
                            H->dt[c], H->recx, H->recy);
-        if (H->timing) HIPOK(hipEventRecord(H->ev[2], H->stream));
+        if (ev) HIPOK(hipEventRecord(ev[2], H->stream));
         hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
                            H->W[c], H->dt[c], H->W[x], H->crec, H->dt[x], H->rpart);
-        if (H->timing) HIPOK(hipEventRecord(H->ev[3], H->stream));
+        if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
         hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
                            slot, H->flag);
-        if (H->timing) HIPOK(hipEventRecord(H->ev[4], H->stream));
+        if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
         hipLaunchKernelGGL(hb::k_update, dim3(P.nc), dim3(256), H->upd_lds, H->stream, P, H->h[c], H->b[c], H->recx,
                            H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
-        if (H->timing) {
-            HIPOK(hipEventRecord(H->ev[5], H->stream));
-            HIPOK(hipEventSynchronize(H->ev[5]));
-            for (int k = 0; k < NKERN; k++) {
-                float ms = 0.f;
-                HIPOK(hipEventElapsedTime(&ms, H->ev[k], H->ev[k + 1]));
-                H->kms[k] += ms;
-                H->klaunch[k]++;
-            }
-        }
+        if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
         HIPOK(hipGetLastError());
         H->cur = x;
         H->step++;
     }
+    return HB_OK;
+}
+
+// fold the recorded event sets into the per-kernel sums
+static int collect_times(hb_ugks *H)
+{
+    if (!H->tused) return HB_OK;
+    HIPOK(hipEventSynchronize(H->tev[H->tused - 1]));
+    for (size_t s = 0; s < H->tused; s += NKERN + 1)
+        for (int k = 0; k < NKERN; k++) {
+            float ms = 0.f;
+            HIPOK(hipEventElapsedTime(&ms, H->tev[s + k], H->tev[s + k + 1]));
+            H->kms[k] += ms;
+            H->klaunch[k]++;
+        }
+    H->tused = 0;
     return HB_OK;
 }
 
@@ -513,8 +532,8 @@ int hb_ugks_enable_timing(hb_handle H, int on)
 {
     if (!H) return HB_EINVAL;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
-    if (on && !H->ev[0])
-        for (auto &e : H->ev) HIPOK(hipEventCreate(&e));
+    if (H->tused) HIPOK(hipEventSynchronize(H->tev[H->tused - 1]));
+    H->tused = 0;
     H->timing = on != 0;
     for (int k = 0; k < NKERN; k++) {
         H->kms[k] = 0.0;
@@ -528,6 +547,9 @@ int hb_ugks_kernel_times(hb_handle H, const char **names, long *launches, double
     if (!H) return HB_EINVAL;
     if (!H->has_case) return HB_ESTATE;
     if (capacity < NKERN) return HB_ECAPACITY;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    const int rc = collect_times(H);
+    if (rc != HB_OK) return rc;
     for (int k = 0; k < NKERN; k++) {
         if (names) names[k] = KNAMES[k];
         if (launches) launches[k] = H->klaunch[k];
