@@ -34,6 +34,8 @@ def main():
     ap.add_argument("--st", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -57,6 +59,16 @@ def main():
             sync = torch.cuda.synchronize
     except Exception:  # torch is plumbing only
         pass
+
+    if args.copy_mib > 0:
+        import torch
+        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
+        del src, dst
 
     case = hbcases.shear_cavity(args.kn, args.st)
     log(f"case {case.name}: {case.nc} cells x {case.nv} velocities x {case.NT} levels = {case.updates} updates/step")

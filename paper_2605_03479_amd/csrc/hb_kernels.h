@@ -24,22 +24,29 @@ __device__ inline int xcd_cell(int b, int G)
     return x * per + (x < rem ? x : rem) + k;
 }
 
-__device__ inline double vanleer(double a, double b)
+// 1/x from v_rcp_f64 refined by two Newton steps (within an ulp of IEEE division)
+__device__ inline double rcp_nr(double x)
 {
-    double p = a * b;
-    return p > 0.0 ? 2.0 * p / (a + b) : 0.0;
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
-// Slope along one line of cells at index i (len cells), f(k) = base[k * stride];
-// one-sided at the two wall-adjacent cells, van Leer inside.
-__device__ inline double line_slope(const double *__restrict__ base, long stride, int i, int len, double fi,
-                                    const double *__restrict__ rc)
+__device__ inline double vanleer_fast(double a, double b)
 {
-    if (i == 0) return (base[stride] - fi) * rc[1];
-    if (i == len - 1) return (fi - base[(long)(i - 1) * stride]) * rc[i];
-    double sm = (fi - base[(long)(i - 1) * stride]) * rc[i];
-    double sp = (base[(long)(i + 1) * stride] - fi) * rc[i + 1];
-    return vanleer(sm, sp);
+    const double p = a * b;
+    const double q = 2.0 * p * rcp_nr(a + b);
+    return p > 0.0 ? q : 0.0;
+}
+
+// slope at index i of a line from the values at i-1, i, i+1 (one-sided at the walls)
+__device__ inline double slope3(double fm, double fc, double fp, int i, int len, const double *__restrict__ rc)
+{
+    if (i == 0) return (fp - fc) * rc[1];
+    if (i == len - 1) return (fc - fm) * rc[i];
+    return vanleer_fast((fc - fm) * rc[i], (fp - fc) * rc[i + 1]);
 }
 
 // ---------------------------------------------------------------- K1: moments
@@ -48,7 +55,7 @@ __device__ inline double line_slope(const double *__restrict__ base, long stride
 // x-face and y-face its quadrant is upwind of, plus the cell moments; the
 // wave reduces them through LDS (transpose + row sums) and the four waves
 // combine into the per-face feeds.
-#define K1_ROW 65
+#define K1_ROW 66
 __global__ __launch_bounds__(256) void k_moments(Params P, const double *__restrict__ h,
                                                  const double *__restrict__ b, double *__restrict__ feed)
 {
@@ -71,11 +78,14 @@ __global__ __launch_bounds__(256) void k_moments(Params P, const double *__restr
             const int ap = q * P.Qp + r;
             const double u = P.vu[ap], v = P.vv[ap], w = P.vw[ap];
             const long e = ((long)c * NT + n) * P.nvp + ap;
-            const double hc = h[e], bc = b[e];
-            const double sxh = line_slope(h + e - i * sx, sx, i, P.nx, hc, P.rcx);
-            const double sxb = line_slope(b + e - i * sx, sx, i, P.nx, bc, P.rcx);
-            const double syh = line_slope(h + e - j * sy, sy, j, P.ny, hc, P.rcy);
-            const double syb = line_slope(b + e - j * sy, sy, j, P.ny, bc, P.rcy);
+            const double *hp = h + e, *bp = b + e;
+            const double hc = hp[0], bc = bp[0];
+            const double hW = i > 0 ? hp[-sx] : 0.0, bW = i > 0 ? bp[-sx] : 0.0;
+            const double hE = i < P.nx - 1 ? hp[sx] : 0.0, bE = i < P.nx - 1 ? bp[sx] : 0.0;
+            const double hS = j > 0 ? hp[-sy] : 0.0, bS = j > 0 ? bp[-sy] : 0.0;
+            const double hN = j < P.ny - 1 ? hp[sy] : 0.0, bN = j < P.ny - 1 ? bp[sy] : 0.0;
+            const double sxh = slope3(hW, hc, hE, i, P.nx, P.rcx), sxb = slope3(bW, bc, bE, i, P.nx, P.rcx);
+            const double syh = slope3(hS, hc, hN, j, P.ny, P.rcy), syb = slope3(bS, bc, bN, j, P.ny, P.rcy);
             const double uu = u * u, uv = u * v, vv = v * v;
             const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
                                    w * vv * v};
@@ -128,9 +138,17 @@ __global__ __launch_bounds__(256) void k_moments(Params P, const double *__restr
                 if (k < kn) rb[k * K1_ROW + lane] = acc[k0 + k];
             __syncthreads();
             if (lane < kn) {
-                double s = 0.0;
-                for (int l = 0; l < 64; l++) s += rb[lane * K1_ROW + l];
-                wsum[q][k0 + lane] = s;
+                const double2 *row = reinterpret_cast<const double2 *>(rb + lane * K1_ROW);
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int l = 0; l < 32; l += 2) {
+                    const double2 x0 = row[l], x1 = row[l + 1];
+                    s0 += x0.x;
+                    s1 += x0.y;
+                    s2 += x1.x;
+                    s3 += x1.y;
+                }
+                wsum[q][k0 + lane] = (s0 + s1) + (s2 + s3);
             }
             __syncthreads();
         }
@@ -474,19 +492,21 @@ __device__ inline double local_dt(const Params &P, const double *Wc, int i, int 
     return P.cfl / (nu + P.omega * P.NH);
 }
 
-__device__ inline void cell_eq(const Params &P, const double *Wc, const double *cm, double *out)
+__device__ inline void cell_eq(const Params &P, const double *Wc, const double *cm, double dG, double *out)
 {
     double p[4], q[2];
     prim4(P.K, Wc, p);
     heat_flux_raw(cm, cm + 10, p[1], p[2], q);
     const double s = (1.0 - P.Pr) * 4.0 * p[3] * p[3] / (5.0 * p[0]);
+    const double A = p[0] * p[3] / HB_PI;
     out[0] = p[3];
     out[1] = p[1];
     out[2] = p[2];
-    out[3] = p[0] * p[3] / HB_PI;
-    out[4] = 1.0 / tau_of(P, p[0], p[3]);
-    out[5] = s * q[0];
-    out[6] = s * q[1];
+    out[3] = A;
+    out[4] = A * P.K / (2.0 * p[3]);
+    out[5] = 0.5 * dG / tau_of(P, p[0], p[3]);
+    out[6] = s * q[0];
+    out[7] = s * q[1];
 }
 
 // one thread per cell: macro update (Eq. 29), collision records, residual terms, next local step
@@ -517,8 +537,9 @@ __global__ __launch_bounds__(128) void k_cells(Params P, const double *__restric
             }
             const double *cm = feed + ((long)c * NT + n) * FEED + FEED_CM;
             double *cr = crec + ((long)c * NT + n) * CREC;
-            cell_eq(P, Wc + n * 4, cm, cr);
-            cell_eq(P, Wo + n * 4, cm, cr + 7);
+            cell_eq(P, Wc + n * 4, cm, dG, cr);
+            cell_eq(P, Wo + n * 4, cm, dG, cr + CREC_T);
+            cr[16] = 1.0 / (1.0 + cr[CREC_T + 5]);
         }
         for (int k = 0; k < 4; k++) {
             const double d = Wo[k] - Wc[k];
@@ -559,75 +580,132 @@ __global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart,
 }
 
 // ---------------------------------------------------------------- K5: update
-// One block per cell.  LDS holds the 1-D Maxwellian factor tables of the four
-// faces (merged normal table + one tangential table per upwind side) and of
-// the cell equilibria at k and k+1, for every level.
-struct Lane {
-    double u, v;
-    int iu, iv;
-};
+// One block per cell, templated on the number of levels so the per-level
+// state of a velocity lives in registers.  LDS holds the 1-D Maxwellian factor
+// tables of the four faces (merged normal table + one tangential table per
+// upwind side) and of the cell equilibria at k and k+1, for every level.
 
-__device__ inline double p3_eval(const double *c, double n, double t)
+template <typename Ptr>
+__device__ inline double p3_eval(Ptr c, double n, double t)
 {
     return c[0] + n * (c[1] + n * (c[3] + n * c[6]) + t * (c[4] + n * c[7])) + t * (c[2] + t * (c[5] + t * c[9] + n * c[8]));
 }
 
-// micro flux through one face for this lane: u_n (e Q(n,t) + c4 f0 + c5 s)
-__device__ inline void face_flux(const double *__restrict__ rec, int side, const double *__restrict__ tn,
-                                 const double *__restrict__ tt, int in_, int it_, double un, double ut, double h0,
-                                 double b0, double sh, double sb, double &Hh, double &Hb)
+// Read-only data every lane of the wave reads at the same address: typed in
+// the constant address space so the loads are scalar (SMEM, into SGPRs) and
+// never wait behind the vector loads of the stencil.
+typedef __attribute__((address_space(4))) const double cdouble;
+
+__device__ inline cdouble *wave_uniform(const double *p)
 {
-    const double *s = rec + REC_SIDE + REC_SIDEW * side;
-    const double e = tn[in_] * tt[it_];
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    return (cdouble *)((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// micro flux through one face for this lane: u_n (e Q(n,t) + c4 f0 + c5 s)
+template <typename Ptr>
+__device__ inline void face_flux(Ptr s, double e, double un, double ut, double h0, double b0, double sh, double sb,
+                                 double &Hh, double &Hb)
+{
     const double qh = p3_eval(s + 3, un, ut), qb = p3_eval(s + 13, un, ut);
     Hh = un * (e * qh + s[23] * h0 + s[24] * sh);
     Hb = un * (e * qb + s[23] * b0 + s[24] * sb);
 }
 
-__global__ __launch_bounds__(256) void k_update(Params P, const double *__restrict__ h, const double *__restrict__ b,
-                                                const double *__restrict__ recx, const double *__restrict__ recy,
-                                                const double *__restrict__ crec, const double *__restrict__ dtc,
-                                                double *__restrict__ hn, double *__restrict__ bn)
+// Tables of one cell's block: 4 faces x NT levels x (merged normal, two
+// tangential) + NT levels x (u, v) x (k, k+1) for the cell equilibria.
+template <int NT>
+__device__ inline void build_tables(const Params &P, const double *const fr[4], const double *cr, double *tab)
 {
-    extern __shared__ double tab[];
-    const int c = xcd_cell(blockIdx.x, gridDim.x);
-    const int NT = P.NT, M = P.M, nx = P.nx, ny = P.ny, K = P.K;
-    const int i = c % nx, j = c / nx;
-    // face record pointers: 0 west, 1 east, 2 south, 3 north
-    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
-                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
-    const double *cr = crec + (long)c * NT * CREC;
-    // tables
-    const int ftab = 12 * NT * M;
+    const int M = P.M, ftab = 12 * NT * M;
     for (int t = threadIdx.x; t < 16 * NT * M; t += blockDim.x) {
         const int k = t % M;
         const double x = P.u1[k];
         double lam, U;
         if (t < ftab) {
             const int which = (t / M) % 3, fn = t / (3 * M), n = fn % NT, fs = fn / NT;
-            const double *rec = fr[fs] + n * REC;
-            if (which == 0) {
-                const double *s = rec + REC_SIDE + REC_SIDEW * (x > 0.0 ? 1 : 0);
-                lam = s[0];
-                U = s[1];
-            } else {
-                const double *s = rec + REC_SIDE + REC_SIDEW * (which - 1);
-                lam = s[0];
-                U = s[2];
-            }
+            const double *sd = fr[fs] + n * REC + REC_SIDE + REC_SIDEW * (which == 0 ? (x > 0.0 ? 1 : 0) : which - 1);
+            lam = sd[0];
+            U = which == 0 ? sd[1] : sd[2];
         } else {
             const int tt = t - ftab, which = (tt / M) % 4, n = tt / (4 * M);
-            const double *cc = cr + n * CREC + (which >= 2 ? 7 : 0);
+            const double *cc = cr + n * CREC + (which >= 2 ? CREC_T : 0);
             lam = cc[0];
             U = (which & 1) ? cc[2] : cc[1];
         }
         tab[t] = exp(-lam * (x - U) * (x - U));
     }
+}
+
+// Spectral source and semi-implicit collision (Eq. 30) for one velocity at all
+// levels, then the store of h^{k+1}, b^{k+1}.
+template <int NT>
+__device__ inline void collide_store(const Params &P, const double *cr, const double *ctab, double dG, double u,
+                                     double v, int iu, int iv, const double *hk, const double *bk, const double *dh,
+                                     const double *db, double *hn, double *bn, long e0)
+{
+    const int M = P.M;
+    const double kh = P.K - 5.0, kb = P.K - 3.0, dgw = dG * P.omega;
+#pragma unroll
+    for (int n = 0; n < NT; n++) {
+        double Eh = 0.0, Eb = 0.0;
+#pragma unroll
+        for (int m = 0; m < NT; m++) {
+            Eh += P.E[n * NT + m] * hk[m];
+            Eb += P.E[n * NT + m] * bk[m];
+        }
+        const double *cc = cr + n * CREC;
+        const double *ct = ctab + n * 4 * M;
+        double heq[2], beq[2];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; s2++) {
+            const double *q = cc + CREC_T * s2;
+            const double lam2 = 2.0 * q[0];
+            const double e = ct[(2 * s2) * M + iu] * ct[(2 * s2 + 1) * M + iv];
+            const double cu = u - q[1], cv = v - q[2];
+            const double c2 = cu * cu + cv * cv, cq = cu * q[6] + cv * q[7];
+            heq[s2] = e * q[3] * (1.0 + cq * (lam2 * c2 + kh));
+            beq[s2] = e * q[4] * (1.0 + cq * (lam2 * c2 + kb));
+        }
+        const double a0 = cc[5], a1 = cc[CREC_T + 5], rden = cc[16];
+        const double hnew = (hk[n] - dG * dh[n] - dgw * Eh + a1 * heq[1] + a0 * (heq[0] - hk[n])) * rden;
+        const double bnew = (bk[n] - dG * db[n] - dgw * Eb + a1 * beq[1] + a0 * (beq[0] - bk[n])) * rden;
+        hn[e0 + (long)n * P.nvp] = hnew;
+        bn[e0 + (long)n * P.nvp] = bnew;
+    }
+}
+
+// Interior cells (2 <= i <= nx-3, 2 <= j <= ny-3): every stencil value exists
+// and every slope is limited, so the per-velocity work is straight-line code.
+template <int NT>
+#ifndef HB_UPD_MINBLK
+#define HB_UPD_MINBLK 2
+#endif
+__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const double *__restrict__ h,
+                                                       const double *__restrict__ b, const double *__restrict__ recx,
+                                                       const double *__restrict__ recy,
+                                                       const double *__restrict__ crec,
+                                                       const double *__restrict__ dtc, double *__restrict__ hn,
+                                                       double *__restrict__ bn)
+{
+    extern __shared__ double tab[];
+    const int nxi = P.nx - 4;
+    const int ci = xcd_cell(blockIdx.x, gridDim.x);
+    const int i = 2 + ci % nxi, j = 2 + ci / nxi;
+    const int M = P.M, nx = P.nx;
+    const int c = j * nx + i;
+    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
+                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
+    const double *cr = crec + (long)c * NT * CREC;
+    build_tables<NT>(P, fr, cr, tab);
     __syncthreads();
-    const double *ctab = tab + ftab;
+    const double *ctab = tab + 12 * NT * M;
     const long sx = (long)NT * P.nvp, sy = (long)nx * NT * P.nvp;
     const double dG = dtc[c];
-    const double om = P.omega;
+    const double rdx = P.rdx[i], rdy = P.rdy[j];
+    const double *rcx = P.rcx, *rcy = P.rcy;
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
@@ -636,104 +714,181 @@ __global__ __launch_bounds__(256) void k_update(Params P, const double *__restri
         const int iu = P.viu[ap], iv = P.viv[ap];
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
-        double hk[HB_NTMAX], bk[HB_NTMAX], dh[HB_NTMAX], db[HB_NTMAX];
+        const int fxo = su ? 1 : 0, fxi = 1 - fxo, fyo = sv ? 3 : 2, fyi = 5 - fyo;
+        const int iU = su ? i - 1 : i + 1, jV = sv ? j - 1 : j + 1;
+        const long oU = su ? -sx : sx, oV = sv ? -sy : sy;
+        const double dxo = su ? P.xf[i + 1] - P.xc[i] : P.xf[i] - P.xc[i];
+        const double dyo = sv ? P.yf[j + 1] - P.yc[j] : P.yf[j] - P.yc[j];
+        const double dxi = su ? P.xf[i] - P.xc[iU] : P.xf[i + 1] - P.xc[iU];
+        const double dyi = sv ? P.yf[j] - P.yc[jV] : P.yf[j + 1] - P.yc[jV];
+        // limiter reciprocal centre distances: own cell and the two upwind neighbours
+        const double rxm = rcx[i], rxp = rcx[i + 1], rym = rcy[j], ryp = rcy[j + 1];
+        const double rUm = rcx[iU], rUp = rcx[iU + 1], rVm = rcy[jV], rVp = rcy[jV + 1];
+        double hk[NT], bk[NT], dh[NT], db[NT];
+        const long e0 = (long)c * NT * P.nvp + ap;
+#pragma unroll
         for (int n = 0; n < NT; n++) {
-            const long e = ((long)c * NT + n) * P.nvp + ap;
-            const double hc = h[e], bc = b[e];
+            const double *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const double hc = hp[0], bc = bp[0];
+            const double hW = hp[-sx], bW = bp[-sx], hE = hp[sx], bE = bp[sx];
+            const double hS = hp[-sy], bS = bp[-sy], hN = hp[sy], bN = bp[sy];
+            // upwind x-neighbour: far value and diagonals; upwind y-neighbour likewise
+            const double *hq = hp + oU, *bq = bp + oU;
+            const double hUF = hq[oU], bUF = bq[oU], hUs = hq[-sy], bUs = bq[-sy], hUn = hq[sy], bUn = bq[sy];
+            const double *hr = hp + oV, *br = bp + oV;
+            const double hVF = hr[oV], bVF = br[oV], hVw = hr[-sx], bVw = br[-sx], hVe = hr[sx], bVe = br[sx];
             hk[n] = hc;
             bk[n] = bc;
-            const double sxh = line_slope(h + e - i * sx, sx, i, nx, hc, P.rcx);
-            const double sxb = line_slope(b + e - i * sx, sx, i, nx, bc, P.rcx);
-            const double syh = line_slope(h + e - j * sy, sy, j, ny, hc, P.rcy);
-            const double syb = line_slope(b + e - j * sy, sy, j, ny, bc, P.rcy);
+            const double sxh = vanleer_fast((hc - hW) * rxm, (hE - hc) * rxp);
+            const double sxb = vanleer_fast((bc - bW) * rxm, (bE - bc) * rxp);
+            const double syh = vanleer_fast((hc - hS) * rym, (hN - hc) * ryp);
+            const double syb = vanleer_fast((bc - bS) * rym, (bN - bc) * ryp);
             const double sh = u * sxh + v * syh, sb = u * sxb + v * syb;
-            double Hx_out, Bx_out, Hx_in, Bx_in, Hy_out, By_out, Hy_in, By_in;
-            // ---- x faces (normal u, tangential v)
-            {
-                const int fo = su ? 1 : 0, fi_ = su ? 0 : 1;
-                const double xfo = su ? P.xf[i + 1] : P.xf[i];
-                const double *tbo = tab + (fo * NT + n) * 3 * M;
-                face_flux(fr[fo] + n * REC, su, tbo, tbo + (1 + su) * M, iu, iv, u, v, hc + sxh * (xfo - P.xc[i]),
-                          bc + sxb * (xfo - P.xc[i]), sh, sb, Hx_out, Bx_out);
-                const double *tbi = tab + (fi_ * NT + n) * 3 * M;
-                const bool wall = su ? (i == 0) : (i == nx - 1);
-                if (wall) {
-                    face_flux(fr[fi_] + n * REC, su, tbi, tbi + (1 + su) * M, iu, iv, u, v, 0.0, 0.0, 0.0, 0.0, Hx_in,
-                              Bx_in);
-                } else {
-                    const int iU = su ? i - 1 : i + 1;
-                    const long eU = e + (su ? -sx : sx);
-                    const double hU = h[eU], bU = b[eU];
-                    const double sxhU = line_slope(h + eU - iU * sx, sx, iU, nx, hU, P.rcx);
-                    const double sxbU = line_slope(b + eU - iU * sx, sx, iU, nx, bU, P.rcx);
-                    const double syhU = line_slope(h + eU - j * sy, sy, j, ny, hU, P.rcy);
-                    const double sybU = line_slope(b + eU - j * sy, sy, j, ny, bU, P.rcy);
-                    const double xfi = su ? P.xf[i] : P.xf[i + 1];
-                    face_flux(fr[fi_] + n * REC, su, tbi, tbi + (1 + su) * M, iu, iv, u, v,
-                              hU + sxhU * (xfi - P.xc[iU]), bU + sxbU * (xfi - P.xc[iU]), u * sxhU + v * syhU,
-                              u * sxbU + v * sybU, Hx_in, Bx_in);
-                }
-            }
-            // ---- y faces (normal v, tangential u)
-            {
-                const int fo = sv ? 3 : 2, fi_ = sv ? 2 : 3;
-                const double yfo = sv ? P.yf[j + 1] : P.yf[j];
-                const double *tbo = tab + (fo * NT + n) * 3 * M;
-                face_flux(fr[fo] + n * REC, sv, tbo, tbo + (1 + sv) * M, iv, iu, v, u, hc + syh * (yfo - P.yc[j]),
-                          bc + syb * (yfo - P.yc[j]), sh, sb, Hy_out, By_out);
-                const double *tbi = tab + (fi_ * NT + n) * 3 * M;
-                const bool wall = sv ? (j == 0) : (j == ny - 1);
-                if (wall) {
-                    face_flux(fr[fi_] + n * REC, sv, tbi, tbi + (1 + sv) * M, iv, iu, v, u, 0.0, 0.0, 0.0, 0.0, Hy_in,
-                              By_in);
-                } else {
-                    const int jU = sv ? j - 1 : j + 1;
-                    const long eU = e + (sv ? -sy : sy);
-                    const double hU = h[eU], bU = b[eU];
-                    const double sxhU = line_slope(h + eU - i * sx, sx, i, nx, hU, P.rcx);
-                    const double sxbU = line_slope(b + eU - i * sx, sx, i, nx, bU, P.rcx);
-                    const double syhU = line_slope(h + eU - jU * sy, sy, jU, ny, hU, P.rcy);
-                    const double sybU = line_slope(b + eU - jU * sy, sy, jU, ny, bU, P.rcy);
-                    const double yfi = sv ? P.yf[j] : P.yf[j + 1];
-                    face_flux(fr[fi_] + n * REC, sv, tbi, tbi + (1 + sv) * M, iv, iu, v, u,
-                              hU + syhU * (yfi - P.yc[jU]), bU + sybU * (yfi - P.yc[jU]), u * sxhU + v * syhU,
-                              u * sxbU + v * sybU, Hy_in, By_in);
-                }
-            }
-            const double east_h = su ? Hx_out : Hx_in, west_h = su ? Hx_in : Hx_out;
-            const double east_b = su ? Bx_out : Bx_in, west_b = su ? Bx_in : Bx_out;
-            const double north_h = sv ? Hy_out : Hy_in, south_h = sv ? Hy_in : Hy_out;
-            const double north_b = sv ? By_out : By_in, south_b = sv ? By_in : By_out;
-            dh[n] = (east_h - west_h) * P.rdx[i] + (north_h - south_h) * P.rdy[j];
-            db[n] = (east_b - west_b) * P.rdx[i] + (north_b - south_b) * P.rdy[j];
+            const double hU = su ? hW : hE, bU = su ? bW : bE;
+            // U's x-slope from (U-1, U, U+1): for su the far value is U-1 and c is U+1
+            const double xm_h = su ? hUF : hc, xp_h = su ? hc : hUF;
+            const double xm_b = su ? bUF : bc, xp_b = su ? bc : bUF;
+            const double sxhU = vanleer_fast((hU - xm_h) * rUm, (xp_h - hU) * rUp);
+            const double sxbU = vanleer_fast((bU - xm_b) * rUm, (xp_b - bU) * rUp);
+            const double syhU = vanleer_fast((hU - hUs) * rym, (hUn - hU) * ryp);
+            const double sybU = vanleer_fast((bU - bUs) * rym, (bUn - bU) * ryp);
+            const double hV = sv ? hS : hN, bV = sv ? bS : bN;
+            const double ym_h = sv ? hVF : hc, yp_h = sv ? hc : hVF;
+            const double ym_b = sv ? bVF : bc, yp_b = sv ? bc : bVF;
+            const double syhV = vanleer_fast((hV - ym_h) * rVm, (yp_h - hV) * rVp);
+            const double sybV = vanleer_fast((bV - ym_b) * rVm, (yp_b - bV) * rVp);
+            const double sxhV = vanleer_fast((hV - hVw) * rxm, (hVe - hV) * rxp);
+            const double sxbV = vanleer_fast((bV - bVw) * rxm, (bVe - bV) * rxp);
+            const double *tbx = tab + (fxo * NT + n) * 3 * M, *tbxi = tab + (fxi * NT + n) * 3 * M;
+            const double *tby = tab + (fyo * NT + n) * 3 * M, *tbyi = tab + (fyi * NT + n) * 3 * M;
+            cdouble *rxo = wave_uniform(fr[fxo] + n * REC + REC_SIDE + REC_SIDEW * su);
+            cdouble *rxi = wave_uniform(fr[fxi] + n * REC + REC_SIDE + REC_SIDEW * su);
+            cdouble *ryo = wave_uniform(fr[fyo] + n * REC + REC_SIDE + REC_SIDEW * sv);
+            cdouble *ryi = wave_uniform(fr[fyi] + n * REC + REC_SIDE + REC_SIDEW * sv);
+            double Hxo, Bxo, Hxi, Bxi, Hyo, Byo, Hyi, Byi;
+            face_flux(rxo, tbx[iu] * tbx[(1 + su) * M + iv], u, v, hc + sxh * dxo, bc + sxb * dxo, sh, sb, Hxo, Bxo);
+            face_flux(ryo, tby[iv] * tby[(1 + sv) * M + iu], v, u, hc + syh * dyo, bc + syb * dyo, sh, sb, Hyo, Byo);
+            face_flux(rxi, tbxi[iu] * tbxi[(1 + su) * M + iv], u, v, hU + sxhU * dxi, bU + sxbU * dxi,
+                      u * sxhU + v * syhU, u * sxbU + v * sybU, Hxi, Bxi);
+            face_flux(ryi, tbyi[iv] * tbyi[(1 + sv) * M + iu], v, u, hV + syhV * dyi, bV + sybV * dyi,
+                      u * sxhV + v * syhV, u * sxbV + v * sybV, Hyi, Byi);
+            const double dxh = su ? (Hxo - Hxi) : (Hxi - Hxo), dxb = su ? (Bxo - Bxi) : (Bxi - Bxo);
+            const double dyh = sv ? (Hyo - Hyi) : (Hyi - Hyo), dyb = sv ? (Byo - Byi) : (Byi - Byo);
+            dh[n] = dxh * rdx + dyh * rdy;
+            db[n] = dxb * rdx + dyb * rdy;
+            __builtin_amdgcn_sched_barrier(0);
         }
-        // spectral source, semi-implicit collision (Eq. 30), write
+        collide_store<NT>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0);
+    }
+}
+
+// Cells within two of a wall (listed in cells[]): the general stencil with
+// one-sided wall slopes and the diffuse-wall inflow.
+template <int NT>
+__global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
+                                                       const double *__restrict__ h, const double *__restrict__ b,
+                                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                                       const double *__restrict__ crec,
+                                                       const double *__restrict__ dtc, double *__restrict__ hn,
+                                                       double *__restrict__ bn)
+{
+    extern __shared__ double tab[];
+    const int c = cells[blockIdx.x];
+    const int M = P.M, nx = P.nx, ny = P.ny;
+    const int i = c % nx, j = c / nx;
+    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
+                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
+    const double *cr = crec + (long)c * NT * CREC;
+    build_tables<NT>(P, fr, cr, tab);
+    __syncthreads();
+    const double *ctab = tab + 12 * NT * M;
+    const long sx = (long)NT * P.nvp, sy = (long)nx * NT * P.nvp;
+    const double dG = dtc[c];
+    const double rdx = P.rdx[i], rdy = P.rdy[j];
+    const double dxe = P.xf[i + 1] - P.xc[i], dxw = P.xf[i] - P.xc[i];
+    const double dyn = P.yf[j + 1] - P.yc[j], dys = P.yf[j] - P.yc[j];
+
+    for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
+        const int r = ap % P.Qp;
+        if (r >= P.Q) continue;
+        const double u = P.vu[ap], v = P.vv[ap];
+        const int iu = P.viu[ap], iv = P.viv[ap];
+        const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
+        const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
+        const int fxo = su ? 1 : 0, fxi = su ? 0 : 1;
+        const int fyo = sv ? 3 : 2, fyi = sv ? 2 : 3;
+        const bool inx_wall = su ? (i == 0) : (i == nx - 1);
+        const bool iny_wall = sv ? (j == 0) : (j == ny - 1);
+        const int iU = su ? i - 1 : i + 1, jV = sv ? j - 1 : j + 1;
+        const long oU = su ? -sx : sx, oV = sv ? -sy : sy;
+        const double dxo = su ? dxe : dxw, dyo = sv ? dyn : dys;
+        const double dxi = inx_wall ? 0.0 : (su ? P.xf[i] - P.xc[iU] : P.xf[i + 1] - P.xc[iU]);
+        const double dyi = iny_wall ? 0.0 : (sv ? P.yf[j] - P.yc[jV] : P.yf[j + 1] - P.yc[jV]);
+        double hk[NT], bk[NT], dh[NT], db[NT];
+        const long e0 = (long)c * NT * P.nvp + ap;
+#pragma unroll 1
         for (int n = 0; n < NT; n++) {
-            double Eh = 0.0, Eb = 0.0;
-            for (int m = 0; m < NT; m++) {
-                Eh += P.E[n * NT + m] * hk[m];
-                Eb += P.E[n * NT + m] * bk[m];
+            const double *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const double hc = hp[0], bc = bp[0];
+            const double hW = i > 0 ? hp[-sx] : 0.0, bW = i > 0 ? bp[-sx] : 0.0;
+            const double hE = i < nx - 1 ? hp[sx] : 0.0, bE = i < nx - 1 ? bp[sx] : 0.0;
+            const double hS = j > 0 ? hp[-sy] : 0.0, bS = j > 0 ? bp[-sy] : 0.0;
+            const double hN = j < ny - 1 ? hp[sy] : 0.0, bN = j < ny - 1 ? bp[sy] : 0.0;
+            hk[n] = hc;
+            bk[n] = bc;
+            const double sxh = slope3(hW, hc, hE, i, nx, P.rcx), sxb = slope3(bW, bc, bE, i, nx, P.rcx);
+            const double syh = slope3(hS, hc, hN, j, ny, P.rcy), syb = slope3(bS, bc, bN, j, ny, P.rcy);
+            const double sh = u * sxh + v * syh, sb = u * sxb + v * syb;
+            const double *tbx = tab + (fxo * NT + n) * 3 * M;
+            const double *tbxi = tab + (fxi * NT + n) * 3 * M;
+            const double *tby = tab + (fyo * NT + n) * 3 * M;
+            const double *tbyi = tab + (fyi * NT + n) * 3 * M;
+            cdouble *rxo = wave_uniform(fr[fxo] + n * REC + REC_SIDE + REC_SIDEW * su);
+            cdouble *rxi = wave_uniform(fr[fxi] + n * REC + REC_SIDE + REC_SIDEW * su);
+            cdouble *ryo = wave_uniform(fr[fyo] + n * REC + REC_SIDE + REC_SIDEW * sv);
+            cdouble *ryi = wave_uniform(fr[fyi] + n * REC + REC_SIDE + REC_SIDEW * sv);
+            double Hxo, Bxo, Hxi, Bxi, Hyo, Byo, Hyi, Byi;
+            face_flux(rxo, tbx[iu] * tbx[(1 + su) * M + iv], u, v, hc + sxh * dxo, bc + sxb * dxo, sh, sb, Hxo, Bxo);
+            face_flux(ryo, tby[iv] * tby[(1 + sv) * M + iu], v, u, hc + syh * dyo, bc + syb * dyo, sh, sb, Hyo, Byo);
+            const double exi = tbxi[iu] * tbxi[(1 + su) * M + iv];
+            if (inx_wall) {
+                face_flux(rxi, exi, u, v, 0.0, 0.0, 0.0, 0.0, Hxi, Bxi);
+            } else {
+                const double hU = su ? hW : hE, bU = su ? bW : bE;
+                const double *hq = hp + oU, *bq = bp + oU;
+                const bool far = su ? (iU > 0) : (iU < nx - 1);
+                const double hF = far ? hq[oU] : 0.0, bF = far ? bq[oU] : 0.0;
+                const double hUs = j > 0 ? hq[-sy] : 0.0, bUs = j > 0 ? bq[-sy] : 0.0;
+                const double hUn = j < ny - 1 ? hq[sy] : 0.0, bUn = j < ny - 1 ? bq[sy] : 0.0;
+                const double sxhU = su ? slope3(hF, hU, hc, iU, nx, P.rcx) : slope3(hc, hU, hF, iU, nx, P.rcx);
+                const double sxbU = su ? slope3(bF, bU, bc, iU, nx, P.rcx) : slope3(bc, bU, bF, iU, nx, P.rcx);
+                const double syhU = slope3(hUs, hU, hUn, j, ny, P.rcy), sybU = slope3(bUs, bU, bUn, j, ny, P.rcy);
+                face_flux(rxi, exi, u, v, hU + sxhU * dxi, bU + sxbU * dxi, u * sxhU + v * syhU, u * sxbU + v * sybU,
+                          Hxi, Bxi);
             }
-            const double *cc = cr + n * CREC;
-            const double *ct = ctab + n * 4 * M;
-            double heq[2], beq[2], itau[2];
-            for (int s = 0; s < 2; s++) {
-                const double *q = cc + 7 * s;
-                const double lam = q[0];
-                const double e = ct[(2 * s) * M + iu] * ct[(2 * s + 1) * M + iv] * q[3];
-                const double cu = u - q[1], cv = v - q[2];
-                const double c2 = cu * cu + cv * cv, cq = cu * q[5] + cv * q[6];
-                heq[s] = e * (1.0 + cq * (2.0 * lam * c2 + K - 5.0));
-                beq[s] = e * (K / (2.0 * lam)) * (1.0 + cq * (2.0 * lam * c2 + K - 3.0));
-                itau[s] = q[4];
+            const double eyi = tbyi[iv] * tbyi[(1 + sv) * M + iu];
+            if (iny_wall) {
+                face_flux(ryi, eyi, v, u, 0.0, 0.0, 0.0, 0.0, Hyi, Byi);
+            } else {
+                const double hV = sv ? hS : hN, bV = sv ? bS : bN;
+                const double *hq = hp + oV, *bq = bp + oV;
+                const bool far = sv ? (jV > 0) : (jV < ny - 1);
+                const double hF = far ? hq[oV] : 0.0, bF = far ? bq[oV] : 0.0;
+                const double hVw = i > 0 ? hq[-sx] : 0.0, bVw = i > 0 ? bq[-sx] : 0.0;
+                const double hVe = i < nx - 1 ? hq[sx] : 0.0, bVe = i < nx - 1 ? bq[sx] : 0.0;
+                const double syhV = sv ? slope3(hF, hV, hc, jV, ny, P.rcy) : slope3(hc, hV, hF, jV, ny, P.rcy);
+                const double sybV = sv ? slope3(bF, bV, bc, jV, ny, P.rcy) : slope3(bc, bV, bF, jV, ny, P.rcy);
+                const double sxhV = slope3(hVw, hV, hVe, i, nx, P.rcx), sxbV = slope3(bVw, bV, bVe, i, nx, P.rcx);
+                face_flux(ryi, eyi, v, u, hV + syhV * dyi, bV + sybV * dyi, u * sxhV + v * syhV, u * sxbV + v * sybV,
+                          Hyi, Byi);
             }
-            const double den = 1.0 + 0.5 * dG * itau[1];
-            const double hnew = (hk[n] - dG * dh[n] - dG * om * Eh + 0.5 * dG * (heq[1] * itau[1] + (heq[0] - hk[n]) * itau[0])) / den;
-            const double bnew = (bk[n] - dG * db[n] - dG * om * Eb + 0.5 * dG * (beq[1] * itau[1] + (beq[0] - bk[n]) * itau[0])) / den;
-            const long e = ((long)c * NT + n) * P.nvp + ap;
-            hn[e] = hnew;
-            bn[e] = bnew;
+            const double dxh = su ? (Hxo - Hxi) : (Hxi - Hxo), dxb = su ? (Bxo - Bxi) : (Bxi - Bxo);
+            const double dyh = sv ? (Hyo - Hyi) : (Hyi - Hyo), dyb = sv ? (Byo - Byi) : (Byi - Byo);
+            dh[n] = dxh * rdx + dyh * rdy;
+            db[n] = dxb * rdx + dyb * rdy;
+            __builtin_amdgcn_sched_barrier(0);
         }
+        collide_store<NT>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0);
     }
 }
 

@@ -19,8 +19,10 @@ constexpr int REC_SIDE = 4;   // [0..3] macro flux F, global frame
 constexpr int REC_SIDEW = 25; // per side: lam, Un, Ut, Qh[10], Qb[10], c4, c5
 constexpr int REC = 56;       // side 0 = velocities with u_n < 0, side 1 = u_n > 0
 
-// per (cell, level) collision record, K3 -> K5: for W^k then W^{k+1}:
-// lam, U, V, rho lam / pi, 1/tau, s q_x, s q_y  (s = (1-Pr) 4 lam^2 / (5 rho))
-constexpr int CREC = 16;
+// per (cell, level) collision record, K3 -> K5: for W^k at [0..7], W^{k+1} at [8..15]:
+// lam, U, V, A = rho lam/pi, A K/(2 lam), dG/(2 tau), s q_x, s q_y
+// (s = (1-Pr) 4 lam^2 / (5 rho)); then [16] = 1/(1 + dG/(2 tau^{k+1})).
+constexpr int CREC_T = 8;
+constexpr int CREC = 20;
 
 }  // namespace hb

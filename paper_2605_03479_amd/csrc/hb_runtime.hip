@@ -50,6 +50,8 @@ struct hb_ugks {
     long step = 0;
     int cells_blocks = 0;
     size_t upd_lds = 0;
+    int n_int = 0, n_bnd = 0;  // interior cells (>= 2 from every wall) and the boundary ring
+    int *bnd_cells = nullptr;
     std::vector<int> perm;  // natural alpha -> internal alpha'
     // timing: one set of NKERN + 1 events per timed step, read back lazily
     bool timing = false;
@@ -82,6 +84,54 @@ static int dalloc(hb_ugks *H, void **p, size_t nbytes)
     H->bufs.push_back({*p, nbytes});
     H->bytes += nbytes;
     return HB_OK;
+}
+
+// the update kernels are compiled for each admissible number of levels
+template <int NT>
+static int set_update_lds(size_t bytes)
+{
+    if (bytes <= 64 * 1024) return HB_OK;
+    if (hipFuncSetAttribute((const void *)hb::k_update_int<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess ||
+        hipFuncSetAttribute((const void *)hb::k_update_bnd<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess)
+        return HB_EDEVICE;
+    return HB_OK;
+}
+
+static int update_lds_attr(int NT, size_t bytes)
+{
+    switch (NT) {
+    case 1: return set_update_lds<1>(bytes);
+    case 3: return set_update_lds<3>(bytes);
+    case 5: return set_update_lds<5>(bytes);
+    case 7: return set_update_lds<7>(bytes);
+    case 9: return set_update_lds<9>(bytes);
+    default: return set_update_lds<11>(bytes);
+    }
+}
+
+template <int NT>
+static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x)
+{
+    if (H->n_int > 0)
+        hipLaunchKernelGGL(hb::k_update_int<NT>, dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, H->h[c], H->b[c],
+                           H->recx, H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+    if (H->n_bnd > 0)
+        hipLaunchKernelGGL(hb::k_update_bnd<NT>, dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P, H->bnd_cells,
+                           H->h[c], H->b[c], H->recx, H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+}
+
+static void launch_update(hb_ugks *H, const hb::Params &P, int c, int x)
+{
+    switch (P.NT) {
+    case 1: launch_update_t<1>(H, P, c, x); break;
+    case 3: launch_update_t<3>(H, P, c, x); break;
+    case 5: launch_update_t<5>(H, P, c, x); break;
+    case 7: launch_update_t<7>(H, P, c, x); break;
+    case 9: launch_update_t<9>(H, P, c, x); break;
+    default: launch_update_t<11>(H, P, c, x); break;
+    }
 }
 
 extern "C" {
@@ -298,11 +348,19 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->rpart, (size_t)H->cells_blocks * 4, double);
     ALLOC(H->ring, (size_t)RING * 4, double);
     ALLOC(H->flag, 1, int);
+    std::vector<int> bnd;
+    for (int jj = 0; jj < ny; jj++)
+        for (int ii = 0; ii < nx; ii++)
+            if (ii < 2 || ii > nx - 3 || jj < 2 || jj > ny - 3) bnd.push_back(jj * nx + ii);
+    H->n_bnd = (int)bnd.size();
+    H->n_int = P.nc - H->n_bnd;
+    ALLOC(H->bnd_cells, bnd.size(), int);
 #undef ALLOC
     HIPOK(hipMemcpy(H->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->veli, veli.data(), veli.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPOK(hipMemset(H->flag, 0, sizeof(int)));
+    HIPOK(hipMemcpy(H->bnd_cells, bnd.data(), bnd.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPOK(hipMemset(H->ring, 0, sizeof(double) * RING * 4));
     P.xf = H->geo;
     P.yf = H->geo + (nx + 1);
@@ -324,9 +382,13 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
         free_case(H);
         return HB_EINVAL;
     }
-    if (H->upd_lds > 64 * 1024)
-        HIPOK(hipFuncSetAttribute((const void *)hb::k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)H->upd_lds));
+    {
+        const int rcl = update_lds_attr(NT, H->upd_lds);
+        if (rcl != HB_OK) {
+            free_case(H);
+            return rcl;
+        }
+    }
     H->cur = 0;
     H->step = 0;
     const long tot = (long)nel;
@@ -375,8 +437,7 @@ int hb_ugks_pseudo_step(hb_handle H, int nsteps)
         hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
                            slot, H->flag);
         if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
-        hipLaunchKernelGGL(hb::k_update, dim3(P.nc), dim3(256), H->upd_lds, H->stream, P, H->h[c], H->b[c], H->recx,
-                           H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+        launch_update(H, P, c, x);
         if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
         HIPOK(hipGetLastError());
         H->cur = x;

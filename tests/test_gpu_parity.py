@@ -4,7 +4,7 @@ oracle on the same seeded inputs, element by element.
 Tolerance: relative L-inf <= 1e-12 in FP64, where "relative" divides the
 largest absolute difference by the largest deviation of the oracle's result
 from the uniform rest state (the signal the step computes; the rest state
-itself is common to both sides).  Harmonics compare per variable: the largest
+itself is common to both sides), floored at 1% of the state's magnitude.  Harmonics compare per variable: the largest
 |difference| over k and cells against the variable's harmonic signal, the
 largest |qhat_k| over k and cells (k = 0 of rho and T: deviation from rest).
 Per-k normalisation is not used because a small harmonic (the O(amplitude)
@@ -37,7 +37,10 @@ def _rest_like(oracle_state):
 
 
 def _rel(a, r, rest):
-    scale = np.max(np.abs(r - rest))
+    """max |a - r| over the signal max |r - rest|, but never over less than 1%
+    of the state itself: 1e-12 of a signal that is 1e-3 of |h| would ask for
+    agreement below an ulp of h."""
+    scale = max(np.max(np.abs(r - rest)), 1e-2 * np.max(np.abs(r)))
     return np.max(np.abs(a - r)) / scale, scale
 
 
