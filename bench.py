@@ -7,6 +7,11 @@ HBM.  value = cell x velocity x level updates per second.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
+                  [--precision fp64|mixed] [--no-extra] [--copy-mib N]
+Besides the headline (FP64), the JSON line carries secondary measurements:
+the same case in the mixed form (FP32 storage of the deviation from the rest
+Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
+thermal cavity in the mixed form.
 """
 import argparse
 import json
@@ -25,6 +30,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def timed_run(hb, case, prec, stream, sync, steps, warmup):
+    """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
+    handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
+    s = hb.Solver(case, device=0, stream=stream, precision=prec)
+    s.step(warmup)
+    s.residual()  # synchronises the handle's stream
+    if sync:
+        sync()
+    s.enable_timing(True)
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.residual()
+    if sync:
+        sync()
+    t1 = time.perf_counter()
+    kt = s.kernel_times()
+    res = s.residual()
+    s.close()
+    return (t1 - t0) * 1e3 / steps, kt, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -34,6 +60,8 @@ def main():
     ap.add_argument("--st", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -70,24 +98,10 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
+    prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
     case = hbcases.shear_cavity(args.kn, args.st)
     log(f"case {case.name}: {case.nc} cells x {case.nv} velocities x {case.NT} levels = {case.updates} updates/step")
-    s = hb.Solver(case, device=0, stream=stream)
-    s.step(args.warmup)
-    s.residual()  # synchronises the handle's stream
-    if sync:
-        sync()
-    s.enable_timing(True)
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    s.residual()
-    if sync:
-        sync()
-    t1 = time.perf_counter()
-    kt = s.kernel_times()
-    res = s.residual()
-    s.close()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step, kt, res = timed_run(hb, case, prec, stream, sync, args.steps, args.warmup)
     ups = case.updates / (ms_step * 1e-3)
     log(f"ms/step {ms_step:.4f}  updates/s {ups:.4e}  residual {res}")
     for k, (n, ms) in kt.items():
@@ -96,7 +110,8 @@ def main():
     # roofline of the dominant kernel: algorithmic HBM bytes per launch
     #   update : read h, b and write h, b once per (cell, velocity, level) -> 4 x 8 B
     #   moments: read h, b once -> 2 x 8 B
-    algo_bytes = {"update": 32.0 * case.updates, "moments": 16.0 * case.updates}
+    wb = 4.0 if prec == hb.HB_MIXED else 8.0  # bytes per stored word of h or b
+    algo_bytes = {"update": 4 * wb * case.updates, "moments": 2 * wb * case.updates}
     dom = max(kt, key=lambda k: kt[k][1])
     n_dom, ms_dom = kt[dom]
     avg_s = ms_dom / n_dom * 1e-3
@@ -108,7 +123,7 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2)}
-    step_bytes = 48.0 * case.updates  # moments (2 words) + update (4 words) per update
+    step_bytes = 6 * wb * case.updates  # moments (2 words) + update (4 words) per update
     kernels = {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt.items()}
 
     cpu = None
@@ -130,16 +145,33 @@ def main():
                "sample": f"{steps} pseudo steps of the same 64x64x32^2 NH=1 case ({dt:.1f} s)"}
         log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads")
 
+    extra = []
+    if not args.no_extra:
+        others = []
+        if prec == hb.HB_FP64:
+            others.append((case, hb.HB_MIXED, "mixed"))
+        th = hbcases.thermal_cavity(1.0, 1.0)
+        others.append((th, hb.HB_MIXED, "mixed"))
+        for c2, p2, pname in others:
+            steps2 = max(10, min(args.steps, 60))
+            ms2, kt2, _ = timed_run(hb, c2, p2, stream, sync, steps2, 5)
+            extra.append({"workload": c2.name, "precision": pname, "updates_per_s": c2.updates / (ms2 * 1e-3),
+                          "ms_per_step": ms2, "steps": steps2,
+                          "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt2.items()}})
+            log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
+
     out = {
         "metric": METRIC, "value": ups, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == hb.HB_FP64 else "f32-storage/f64-arith",
+        "data": "synthetic",
         "config": {"workload": case.name, "cells": case.nc, "velocities": case.nv, "levels": case.NT,
-                   "Kn": case.Kn, "St": case.St, "precision": "fp64"},
+                   "Kn": case.Kn, "St": case.St, "precision": args.precision},
         "effective_GBps_per_step": step_bytes / (ms_step * 1e-3) / 1e9,
         "kernel_avg_us": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
 

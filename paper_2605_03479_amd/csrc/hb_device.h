@@ -22,6 +22,7 @@ struct Params {
     // velocity grid: 1-D nodes/weights and per-alpha (internal order) values
     const double *u1, *w1, *vu, *vv, *vw;
     const int *viu, *viv;
+    const double *vref;  // rest Maxwellian per velocity (mixed storage reference)
 };
 
 // W = (rho, rho Un, rho Ut, rho E) -> (rho, Un, Ut, lambda); rho E = rho |U|^2/2 + (2+K) rho/(4 lambda)

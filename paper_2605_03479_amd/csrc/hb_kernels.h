@@ -24,6 +24,28 @@ __device__ inline int xcd_cell(int b, int G)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Storage of (h, b): FP64 values, or FP32 deviations from the rest Maxwellian
+// H_ref = exp(-|u|^2)/pi (B_ref = K/2 H_ref) for the mixed form.  All
+// arithmetic below runs in FP64 either way.
+template <typename TS>
+__device__ inline double ldv(const TS *p, long off, double ref)
+{
+    if constexpr (sizeof(TS) == 4) return static_cast<double>(p[off]) + ref;
+    else return p[off];
+}
+template <typename TS>
+__device__ inline void stv(TS *p, long off, double v, double ref)
+{
+    if constexpr (sizeof(TS) == 4) p[off] = static_cast<float>(v - ref);
+    else p[off] = v;
+}
+template <typename TS>
+__device__ inline double href_of(const Params &P, int ap)
+{
+    if constexpr (sizeof(TS) == 4) return P.vref[ap];
+    else return 0.0;
+}
+
 // 1/x from v_rcp_f64 refined by two Newton steps (within an ulp of IEEE division)
 __device__ inline double rcp_nr(double x)
 {
@@ -56,8 +78,9 @@ __device__ inline double slope3(double fm, double fc, double fp, int i, int len,
 // wave reduces them through LDS (transpose + row sums) and the four waves
 // combine into the per-face feeds.
 #define K1_ROW 66
-__global__ __launch_bounds__(256) void k_moments(Params P, const double *__restrict__ h,
-                                                 const double *__restrict__ b, double *__restrict__ feed)
+template <typename TS>
+__global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                                 double *__restrict__ feed)
 {
     __shared__ double red[4][28 * K1_ROW];
     __shared__ double wsum[4][NMOM];
@@ -78,12 +101,13 @@ __global__ __launch_bounds__(256) void k_moments(Params P, const double *__restr
             const int ap = q * P.Qp + r;
             const double u = P.vu[ap], v = P.vv[ap], w = P.vw[ap];
             const long e = ((long)c * NT + n) * P.nvp + ap;
-            const double *hp = h + e, *bp = b + e;
-            const double hc = hp[0], bc = bp[0];
-            const double hW = i > 0 ? hp[-sx] : 0.0, bW = i > 0 ? bp[-sx] : 0.0;
-            const double hE = i < P.nx - 1 ? hp[sx] : 0.0, bE = i < P.nx - 1 ? bp[sx] : 0.0;
-            const double hS = j > 0 ? hp[-sy] : 0.0, bS = j > 0 ? bp[-sy] : 0.0;
-            const double hN = j < P.ny - 1 ? hp[sy] : 0.0, bN = j < P.ny - 1 ? bp[sy] : 0.0;
+            const TS *hp = h + e, *bp = b + e;
+            const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
+            const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
+            const double hW = i > 0 ? ldv<TS>(hp, -sx, rh) : 0.0, bW = i > 0 ? ldv<TS>(bp, -sx, rb) : 0.0;
+            const double hE = i < P.nx - 1 ? ldv<TS>(hp, sx, rh) : 0.0, bE = i < P.nx - 1 ? ldv<TS>(bp, sx, rb) : 0.0;
+            const double hS = j > 0 ? ldv<TS>(hp, -sy, rh) : 0.0, bS = j > 0 ? ldv<TS>(bp, -sy, rb) : 0.0;
+            const double hN = j < P.ny - 1 ? ldv<TS>(hp, sy, rh) : 0.0, bN = j < P.ny - 1 ? ldv<TS>(bp, sy, rb) : 0.0;
             const double sxh = slope3(hW, hc, hE, i, P.nx, P.rcx), sxb = slope3(bW, bc, bE, i, P.nx, P.rcx);
             const double syh = slope3(hS, hc, hN, j, P.ny, P.rcy), syb = slope3(bS, bc, bN, j, P.ny, P.rcy);
             const double uu = u * u, uv = u * v, vv = v * v;
@@ -509,43 +533,45 @@ __device__ inline void cell_eq(const Params &P, const double *Wc, const double *
     out[7] = s * q[1];
 }
 
-// one thread per cell: macro update (Eq. 29), collision records, residual terms, next local step
+// one thread per (cell, level): macro update (Eq. 29), collision records, and
+// the level-0 residual terms (per-block partial sums, fixed order)
 __global__ __launch_bounds__(128) void k_cells(Params P, const double *__restrict__ feed, const double *__restrict__ recx,
                                                const double *__restrict__ recy, const double *__restrict__ Wk,
                                                const double *__restrict__ dtc, double *__restrict__ Wn,
-                                               double *__restrict__ crec, double *__restrict__ dtn,
-                                               double *__restrict__ rpart)
+                                               double *__restrict__ crec, double *__restrict__ rpart)
 {
     __shared__ double red[4][128];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int NT = P.NT, nx = P.nx;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     double d2[4] = {0, 0, 0, 0};
-    if (c < P.nc) {
-        const int NT = P.NT, nx = P.nx, i = c % nx, j = c / nx;
+    if (t < P.nc * NT) {
+        const int c = t / NT, n = t % NT;
+        const int i = c % nx, j = c / nx;
         const double dG = dtc[c];
         const double *Wc = Wk + (long)c * NT * 4;
-        double *Wo = Wn + (long)c * NT * 4;
-        for (int n = 0; n < NT; n++) {
-            const double *Fw = recx + ((long)(j * (nx + 1) + i) * NT + n) * REC;
-            const double *Fe = recx + ((long)(j * (nx + 1) + i + 1) * NT + n) * REC;
-            const double *Fs = recy + ((long)(j * nx + i) * NT + n) * REC;
-            const double *Fn = recy + ((long)((j + 1) * nx + i) * NT + n) * REC;
-            for (int k = 0; k < 4; k++) {
-                double src = 0.0;
-                for (int mm = 0; mm < NT; mm++) src += P.E[n * NT + mm] * Wc[mm * 4 + k];
-                const double div = (Fe[k] - Fw[k]) * P.rdx[i] + (Fn[k] - Fs[k]) * P.rdy[j];
-                Wo[n * 4 + k] = Wc[n * 4 + k] - dG * (div + P.omega * src);
-            }
-            const double *cm = feed + ((long)c * NT + n) * FEED + FEED_CM;
-            double *cr = crec + ((long)c * NT + n) * CREC;
-            cell_eq(P, Wc + n * 4, cm, dG, cr);
-            cell_eq(P, Wo + n * 4, cm, dG, cr + CREC_T);
-            cr[16] = 1.0 / (1.0 + cr[CREC_T + 5]);
-        }
+        double *Wo = Wn + ((long)c * NT + n) * 4;
+        const double *Fw = recx + ((long)(j * (nx + 1) + i) * NT + n) * REC;
+        const double *Fe = recx + ((long)(j * (nx + 1) + i + 1) * NT + n) * REC;
+        const double *Fs = recy + ((long)(j * nx + i) * NT + n) * REC;
+        const double *Fn = recy + ((long)((j + 1) * nx + i) * NT + n) * REC;
+        double Wnew[4];
         for (int k = 0; k < 4; k++) {
-            const double d = Wo[k] - Wc[k];
-            d2[k] = d * d;
+            double src = 0.0;
+            for (int mm = 0; mm < NT; mm++) src += P.E[n * NT + mm] * Wc[mm * 4 + k];
+            const double div = (Fe[k] - Fw[k]) * P.rdx[i] + (Fn[k] - Fs[k]) * P.rdy[j];
+            Wnew[k] = Wc[n * 4 + k] - dG * (div + P.omega * src);
+            Wo[k] = Wnew[k];
         }
-        dtn[c] = local_dt(P, Wo, i, j);
+        const double *cm = feed + ((long)c * NT + n) * FEED + FEED_CM;
+        double *cr = crec + ((long)c * NT + n) * CREC;
+        cell_eq(P, Wc + n * 4, cm, dG, cr);
+        cell_eq(P, Wnew, cm, dG, cr + CREC_T);
+        cr[16] = 1.0 / (1.0 + cr[CREC_T + 5]);
+        if (n == 0)
+            for (int k = 0; k < 4; k++) {
+                const double d = Wnew[k] - Wc[k];
+                d2[k] = d * d;
+            }
     }
     for (int k = 0; k < 4; k++) red[k][threadIdx.x] = d2[k];
     __syncthreads();
@@ -641,10 +667,10 @@ __device__ inline void build_tables(const Params &P, const double *const fr[4], 
 
 // Spectral source and semi-implicit collision (Eq. 30) for one velocity at all
 // levels, then the store of h^{k+1}, b^{k+1}.
-template <int NT>
+template <int NT, typename TS>
 __device__ inline void collide_store(const Params &P, const double *cr, const double *ctab, double dG, double u,
                                      double v, int iu, int iv, const double *hk, const double *bk, const double *dh,
-                                     const double *db, double *hn, double *bn, long e0)
+                                     const double *db, TS *hn, TS *bn, long e0, double rh, double rb)
 {
     const int M = P.M;
     const double kh = P.K - 5.0, kb = P.K - 3.0, dgw = dG * P.omega;
@@ -672,23 +698,23 @@ __device__ inline void collide_store(const Params &P, const double *cr, const do
         const double a0 = cc[5], a1 = cc[CREC_T + 5], rden = cc[16];
         const double hnew = (hk[n] - dG * dh[n] - dgw * Eh + a1 * heq[1] + a0 * (heq[0] - hk[n])) * rden;
         const double bnew = (bk[n] - dG * db[n] - dgw * Eb + a1 * beq[1] + a0 * (beq[0] - bk[n])) * rden;
-        hn[e0 + (long)n * P.nvp] = hnew;
-        bn[e0 + (long)n * P.nvp] = bnew;
+        stv<TS>(hn, e0 + (long)n * P.nvp, hnew, rh);
+        stv<TS>(bn, e0 + (long)n * P.nvp, bnew, rb);
     }
 }
 
 // Interior cells (2 <= i <= nx-3, 2 <= j <= ny-3): every stencil value exists
 // and every slope is limited, so the per-velocity work is straight-line code.
-template <int NT>
+template <int NT, typename TS>
 #ifndef HB_UPD_MINBLK
 #define HB_UPD_MINBLK 2
 #endif
-__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const double *__restrict__ h,
-                                                       const double *__restrict__ b, const double *__restrict__ recx,
+__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const TS *__restrict__ h,
+                                                       const TS *__restrict__ b, const double *__restrict__ recx,
                                                        const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
-                                                       const double *__restrict__ dtc, double *__restrict__ hn,
-                                                       double *__restrict__ bn)
+                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
+                                                       TS *__restrict__ bn)
 {
     extern __shared__ double tab[];
     const int nxi = P.nx - 4;
@@ -712,6 +738,7 @@ __global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, con
         if (r >= P.Q) continue;
         const double u = P.vu[ap], v = P.vv[ap];
         const int iu = P.viu[ap], iv = P.viv[ap];
+        const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
         const int fxo = su ? 1 : 0, fxi = 1 - fxo, fyo = sv ? 3 : 2, fyi = 5 - fyo;
@@ -728,15 +755,15 @@ __global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, con
         const long e0 = (long)c * NT * P.nvp + ap;
 #pragma unroll
         for (int n = 0; n < NT; n++) {
-            const double *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
-            const double hc = hp[0], bc = bp[0];
-            const double hW = hp[-sx], bW = bp[-sx], hE = hp[sx], bE = bp[sx];
-            const double hS = hp[-sy], bS = bp[-sy], hN = hp[sy], bN = bp[sy];
+            const TS *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
+            const double hW = ldv<TS>(hp, -sx, rh), bW = ldv<TS>(bp, -sx, rb), hE = ldv<TS>(hp, sx, rh), bE = ldv<TS>(bp, sx, rb);
+            const double hS = ldv<TS>(hp, -sy, rh), bS = ldv<TS>(bp, -sy, rb), hN = ldv<TS>(hp, sy, rh), bN = ldv<TS>(bp, sy, rb);
             // upwind x-neighbour: far value and diagonals; upwind y-neighbour likewise
-            const double *hq = hp + oU, *bq = bp + oU;
-            const double hUF = hq[oU], bUF = bq[oU], hUs = hq[-sy], bUs = bq[-sy], hUn = hq[sy], bUn = bq[sy];
-            const double *hr = hp + oV, *br = bp + oV;
-            const double hVF = hr[oV], bVF = br[oV], hVw = hr[-sx], bVw = br[-sx], hVe = hr[sx], bVe = br[sx];
+            const TS *hq = hp + oU, *bq = bp + oU;
+            const double hUF = ldv<TS>(hq, oU, rh), bUF = ldv<TS>(bq, oU, rb), hUs = ldv<TS>(hq, -sy, rh), bUs = ldv<TS>(bq, -sy, rb), hUn = ldv<TS>(hq, sy, rh), bUn = ldv<TS>(bq, sy, rb);
+            const TS *hr = hp + oV, *br = bp + oV;
+            const double hVF = ldv<TS>(hr, oV, rh), bVF = ldv<TS>(br, oV, rb), hVw = ldv<TS>(hr, -sx, rh), bVw = ldv<TS>(br, -sx, rb), hVe = ldv<TS>(hr, sx, rh), bVe = ldv<TS>(br, sx, rb);
             hk[n] = hc;
             bk[n] = bc;
             const double sxh = vanleer_fast((hc - hW) * rxm, (hE - hc) * rxp);
@@ -778,19 +805,19 @@ __global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, con
             db[n] = dxb * rdx + dyb * rdy;
             __builtin_amdgcn_sched_barrier(0);
         }
-        collide_store<NT>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0);
+        collide_store<NT, TS>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0, rh, rb);
     }
 }
 
 // Cells within two of a wall (listed in cells[]): the general stencil with
 // one-sided wall slopes and the diffuse-wall inflow.
-template <int NT>
+template <int NT, typename TS>
 __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
-                                                       const double *__restrict__ h, const double *__restrict__ b,
+                                                       const TS *__restrict__ h, const TS *__restrict__ b,
                                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
-                                                       const double *__restrict__ dtc, double *__restrict__ hn,
-                                                       double *__restrict__ bn)
+                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
+                                                       TS *__restrict__ bn)
 {
     extern __shared__ double tab[];
     const int c = cells[blockIdx.x];
@@ -813,6 +840,7 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
         if (r >= P.Q) continue;
         const double u = P.vu[ap], v = P.vv[ap];
         const int iu = P.viu[ap], iv = P.viv[ap];
+        const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
         const int fxo = su ? 1 : 0, fxi = su ? 0 : 1;
@@ -828,12 +856,12 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
         const long e0 = (long)c * NT * P.nvp + ap;
 #pragma unroll 1
         for (int n = 0; n < NT; n++) {
-            const double *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
-            const double hc = hp[0], bc = bp[0];
-            const double hW = i > 0 ? hp[-sx] : 0.0, bW = i > 0 ? bp[-sx] : 0.0;
-            const double hE = i < nx - 1 ? hp[sx] : 0.0, bE = i < nx - 1 ? bp[sx] : 0.0;
-            const double hS = j > 0 ? hp[-sy] : 0.0, bS = j > 0 ? bp[-sy] : 0.0;
-            const double hN = j < ny - 1 ? hp[sy] : 0.0, bN = j < ny - 1 ? bp[sy] : 0.0;
+            const TS *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
+            const double hW = i > 0 ? ldv<TS>(hp, -sx, rh) : 0.0, bW = i > 0 ? ldv<TS>(bp, -sx, rb) : 0.0;
+            const double hE = i < nx - 1 ? ldv<TS>(hp, sx, rh) : 0.0, bE = i < nx - 1 ? ldv<TS>(bp, sx, rb) : 0.0;
+            const double hS = j > 0 ? ldv<TS>(hp, -sy, rh) : 0.0, bS = j > 0 ? ldv<TS>(bp, -sy, rb) : 0.0;
+            const double hN = j < ny - 1 ? ldv<TS>(hp, sy, rh) : 0.0, bN = j < ny - 1 ? ldv<TS>(bp, sy, rb) : 0.0;
             hk[n] = hc;
             bk[n] = bc;
             const double sxh = slope3(hW, hc, hE, i, nx, P.rcx), sxb = slope3(bW, bc, bE, i, nx, P.rcx);
@@ -855,11 +883,11 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
                 face_flux(rxi, exi, u, v, 0.0, 0.0, 0.0, 0.0, Hxi, Bxi);
             } else {
                 const double hU = su ? hW : hE, bU = su ? bW : bE;
-                const double *hq = hp + oU, *bq = bp + oU;
+                const TS *hq = hp + oU, *bq = bp + oU;
                 const bool far = su ? (iU > 0) : (iU < nx - 1);
-                const double hF = far ? hq[oU] : 0.0, bF = far ? bq[oU] : 0.0;
-                const double hUs = j > 0 ? hq[-sy] : 0.0, bUs = j > 0 ? bq[-sy] : 0.0;
-                const double hUn = j < ny - 1 ? hq[sy] : 0.0, bUn = j < ny - 1 ? bq[sy] : 0.0;
+                const double hF = far ? ldv<TS>(hq, oU, rh) : 0.0, bF = far ? ldv<TS>(bq, oU, rb) : 0.0;
+                const double hUs = j > 0 ? ldv<TS>(hq, -sy, rh) : 0.0, bUs = j > 0 ? ldv<TS>(bq, -sy, rb) : 0.0;
+                const double hUn = j < ny - 1 ? ldv<TS>(hq, sy, rh) : 0.0, bUn = j < ny - 1 ? ldv<TS>(bq, sy, rb) : 0.0;
                 const double sxhU = su ? slope3(hF, hU, hc, iU, nx, P.rcx) : slope3(hc, hU, hF, iU, nx, P.rcx);
                 const double sxbU = su ? slope3(bF, bU, bc, iU, nx, P.rcx) : slope3(bc, bU, bF, iU, nx, P.rcx);
                 const double syhU = slope3(hUs, hU, hUn, j, ny, P.rcy), sybU = slope3(bUs, bU, bUn, j, ny, P.rcy);
@@ -871,11 +899,11 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
                 face_flux(ryi, eyi, v, u, 0.0, 0.0, 0.0, 0.0, Hyi, Byi);
             } else {
                 const double hV = sv ? hS : hN, bV = sv ? bS : bN;
-                const double *hq = hp + oV, *bq = bp + oV;
+                const TS *hq = hp + oV, *bq = bp + oV;
                 const bool far = sv ? (jV > 0) : (jV < ny - 1);
-                const double hF = far ? hq[oV] : 0.0, bF = far ? bq[oV] : 0.0;
-                const double hVw = i > 0 ? hq[-sx] : 0.0, bVw = i > 0 ? bq[-sx] : 0.0;
-                const double hVe = i < nx - 1 ? hq[sx] : 0.0, bVe = i < nx - 1 ? bq[sx] : 0.0;
+                const double hF = far ? ldv<TS>(hq, oV, rh) : 0.0, bF = far ? ldv<TS>(bq, oV, rb) : 0.0;
+                const double hVw = i > 0 ? ldv<TS>(hq, -sx, rh) : 0.0, bVw = i > 0 ? ldv<TS>(bq, -sx, rb) : 0.0;
+                const double hVe = i < nx - 1 ? ldv<TS>(hq, sx, rh) : 0.0, bVe = i < nx - 1 ? ldv<TS>(bq, sx, rb) : 0.0;
                 const double syhV = sv ? slope3(hF, hV, hc, jV, ny, P.rcy) : slope3(hc, hV, hF, jV, ny, P.rcy);
                 const double sybV = sv ? slope3(bF, bV, bc, jV, ny, P.rcy) : slope3(bc, bV, bF, jV, ny, P.rcy);
                 const double sxhV = slope3(hVw, hV, hVe, i, nx, P.rcx), sxbV = slope3(bVw, bV, bVe, i, nx, P.rcx);
@@ -888,12 +916,13 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
             db[n] = dxb * rdx + dyb * rdy;
             __builtin_amdgcn_sched_barrier(0);
         }
-        collide_store<NT>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0);
+        collide_store<NT, TS>(P, cr, ctab, dG, u, v, iu, iv, hk, bk, dh, db, hn, bn, e0, rh, rb);
     }
 }
 
 // ---------------------------------------------------------------- set-up kernels
-__global__ void k_init(Params P, double *h, double *b, double *W)
+template <typename TS>
+__global__ void k_init(Params P, TS *h, TS *b, double *W)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long nel = (long)P.nc * P.NT * P.nvp;
@@ -902,14 +931,29 @@ __global__ void k_init(Params P, double *h, double *b, double *W)
         const bool valid = (ap % P.Qp) < P.Q;
         const double u = P.vu[ap], v = P.vv[ap];
         const double H = valid ? exp(-(u * u + v * v)) / HB_PI : 0.0;
-        h[t] = H;
-        b[t] = 0.5 * P.K * H;
+        if constexpr (sizeof(TS) == 4) {
+            h[t] = 0.0f;  // rest state: deviation from H_ref is zero
+            b[t] = 0.0f;
+        } else {
+            h[t] = H;
+            b[t] = 0.5 * P.K * H;
+        }
     }
     if (t < (long)P.nc * P.NT) {
         W[t * 4 + 0] = 1.0;
         W[t * 4 + 1] = 0.0;
         W[t * 4 + 2] = 0.0;
         W[t * 4 + 3] = (2.0 + P.K) / 4.0;
+    }
+}
+
+// rest Maxwellian per velocity (reference of the mixed storage)
+__global__ void k_vref(Params P, double *vref)
+{
+    const int ap = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ap < P.nvp) {
+        const double u = P.vu[ap], v = P.vv[ap];
+        vref[ap] = ((ap % P.Qp) < P.Q) ? exp(-(u * u + v * v)) / HB_PI : 0.0;
     }
 }
 
@@ -921,7 +965,8 @@ __global__ void k_dt(Params P, const double *W, double *dtc)
 
 // ---------------------------------------------------------------- harmonics
 // per (cell, level): rho, U, V, T/T0 from W; P_xy, q_x, q_y from h, b about U, V
-__global__ __launch_bounds__(256) void k_harm_vars(Params P, const double *__restrict__ h, const double *__restrict__ b,
+template <typename TS>
+__global__ __launch_bounds__(256) void k_harm_vars(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                    const double *__restrict__ W, double *__restrict__ vars)
 {
     __shared__ double red[3][256];
@@ -933,7 +978,8 @@ __global__ __launch_bounds__(256) void k_harm_vars(Params P, const double *__res
         for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
             const long e = ((long)c * P.NT + n) * P.nvp + ap;
             const double w = P.vw[ap], cu = P.vu[ap] - p[1], cv = P.vv[ap] - p[2];
-            const double hh = h[e], en = (cu * cu + cv * cv) * hh + b[e];
+            const double rh = href_of<TS>(P, ap);
+            const double hh = ldv<TS>(h, e, rh), en = (cu * cu + cv * cv) * hh + ldv<TS>(b, e, 0.5 * P.K * rh);
             s0 += w * cu * cv * hh;
             s1 += w * cu * en;
             s2 += w * cv * en;

@@ -43,7 +43,10 @@ struct hb_ugks {
     double *geo = nullptr;  // xf, yf, xc, yc, rdx, rdy, rcx, rcy, u1, w1
     double *vel = nullptr;  // vu, vv, vw
     int *veli = nullptr;    // viu, viv
-    double *h[2]{}, *b[2]{}, *W[2]{}, *dt[2]{};
+    void *h[2]{}, *b[2]{};  // double (FP64) or float deviations from the rest Maxwellian (mixed)
+    double *W[2]{}, *dt[2]{};
+    double *vref = nullptr;
+    std::vector<double> vref_host;
     double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
     int *flag = nullptr;
     int cur = 0;
@@ -87,52 +90,79 @@ static int dalloc(hb_ugks *H, void **p, size_t nbytes)
 }
 
 // the update kernels are compiled for each admissible number of levels
-template <int NT>
-static int set_update_lds(size_t bytes)
+template <int NT, typename TS>
+static int set_update_lds_t(size_t bytes)
 {
     if (bytes <= 64 * 1024) return HB_OK;
-    if (hipFuncSetAttribute((const void *)hb::k_update_int<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void *)hb::k_update_int<NT, TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess ||
-        hipFuncSetAttribute((const void *)hb::k_update_bnd<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipFuncSetAttribute((const void *)hb::k_update_bnd<NT, TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess)
         return HB_EDEVICE;
     return HB_OK;
 }
 
-static int update_lds_attr(int NT, size_t bytes)
+template <typename TS>
+static int update_lds_attr_t(int NT, size_t bytes)
 {
     switch (NT) {
-    case 1: return set_update_lds<1>(bytes);
-    case 3: return set_update_lds<3>(bytes);
-    case 5: return set_update_lds<5>(bytes);
-    case 7: return set_update_lds<7>(bytes);
-    case 9: return set_update_lds<9>(bytes);
-    default: return set_update_lds<11>(bytes);
+    case 1: return set_update_lds_t<1, TS>(bytes);
+    case 3: return set_update_lds_t<3, TS>(bytes);
+    case 5: return set_update_lds_t<5, TS>(bytes);
+    case 7: return set_update_lds_t<7, TS>(bytes);
+    case 9: return set_update_lds_t<9, TS>(bytes);
+    default: return set_update_lds_t<11, TS>(bytes);
     }
 }
 
-template <int NT>
+static int update_lds_attr(int precision, int NT, size_t bytes)
+{
+    return precision == HB_MIXED ? update_lds_attr_t<float>(NT, bytes) : update_lds_attr_t<double>(NT, bytes);
+}
+
+template <int NT, typename TS>
 static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x)
 {
+    const TS *h = (const TS *)H->h[c], *b = (const TS *)H->b[c];
+    TS *hn = (TS *)H->h[x], *bn = (TS *)H->b[x];
     if (H->n_int > 0)
-        hipLaunchKernelGGL(hb::k_update_int<NT>, dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, H->h[c], H->b[c],
-                           H->recx, H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+        hipLaunchKernelGGL((hb::k_update_int<NT, TS>), dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, h, b,
+                           H->recx, H->recy, H->crec, H->dt[c], hn, bn);
     if (H->n_bnd > 0)
-        hipLaunchKernelGGL(hb::k_update_bnd<NT>, dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P, H->bnd_cells,
-                           H->h[c], H->b[c], H->recx, H->recy, H->crec, H->dt[c], H->h[x], H->b[x]);
+        hipLaunchKernelGGL((hb::k_update_bnd<NT, TS>), dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P,
+                           H->bnd_cells, h, b, H->recx, H->recy, H->crec, H->dt[c], hn, bn);
+}
+
+template <typename TS>
+static void launch_update_p(hb_ugks *H, const hb::Params &P, int c, int x)
+{
+    switch (P.NT) {
+    case 1: launch_update_t<1, TS>(H, P, c, x); break;
+    case 3: launch_update_t<3, TS>(H, P, c, x); break;
+    case 5: launch_update_t<5, TS>(H, P, c, x); break;
+    case 7: launch_update_t<7, TS>(H, P, c, x); break;
+    case 9: launch_update_t<9, TS>(H, P, c, x); break;
+    default: launch_update_t<11, TS>(H, P, c, x); break;
+    }
 }
 
 static void launch_update(hb_ugks *H, const hb::Params &P, int c, int x)
 {
-    switch (P.NT) {
-    case 1: launch_update_t<1>(H, P, c, x); break;
-    case 3: launch_update_t<3>(H, P, c, x); break;
-    case 5: launch_update_t<5>(H, P, c, x); break;
-    case 7: launch_update_t<7>(H, P, c, x); break;
-    case 9: launch_update_t<9>(H, P, c, x); break;
-    default: launch_update_t<11>(H, P, c, x); break;
-    }
+    if (H->precision == HB_MIXED) launch_update_p<float>(H, P, c, x);
+    else launch_update_p<double>(H, P, c, x);
 }
+
+static void launch_moments(hb_ugks *H, const hb::Params &P, int c)
+{
+    if (H->precision == HB_MIXED)
+        hipLaunchKernelGGL(hb::k_moments<float>, dim3(P.nc), dim3(256), 0, H->stream, P, (const float *)H->h[c],
+                           (const float *)H->b[c], H->feed);
+    else
+        hipLaunchKernelGGL(hb::k_moments<double>, dim3(P.nc), dim3(256), 0, H->stream, P, (const double *)H->h[c],
+                           (const double *)H->b[c], H->feed);
+}
+
+static size_t elem_bytes(const hb_ugks *H) { return H->precision == HB_MIXED ? sizeof(float) : sizeof(double); }
 
 extern "C" {
 
@@ -169,7 +199,7 @@ int hb_ugks_create(const hb_create_opts *opts, hb_handle *out)
     *out = nullptr;
     hb_create_opts o{0, nullptr, HB_FP64, 0};
     if (opts) o = *opts;
-    if (o.precision != HB_FP64) return HB_EINVAL;
+    if (o.precision != HB_FP64 && o.precision != HB_MIXED) return HB_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
         (void)hipGetLastError();
@@ -322,7 +352,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
 
     const size_t nel = (size_t)P.nc * NT * nvp;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
-    H->cells_blocks = (P.nc + 127) / 128;
+    H->cells_blocks = (P.nc * NT + 127) / 128;
     int rc = HB_OK;
 #define ALLOC(ptr, count, T)                                            \
     do {                                                                \
@@ -336,8 +366,13 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->vel, vel.size(), double);
     ALLOC(H->veli, veli.size(), int);
     for (int s = 0; s < 2; s++) {
-        ALLOC(H->h[s], nel, double);
-        ALLOC(H->b[s], nel, double);
+        if (H->precision == HB_MIXED) {
+            ALLOC(H->h[s], nel, float);
+            ALLOC(H->b[s], nel, float);
+        } else {
+            ALLOC(H->h[s], nel, double);
+            ALLOC(H->b[s], nel, double);
+        }
         ALLOC(H->W[s], (size_t)P.nc * NT * 4, double);
         ALLOC(H->dt[s], P.nc, double);
     }
@@ -348,6 +383,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->rpart, (size_t)H->cells_blocks * 4, double);
     ALLOC(H->ring, (size_t)RING * 4, double);
     ALLOC(H->flag, 1, int);
+    ALLOC(H->vref, nvp, double);
     std::vector<int> bnd;
     for (int jj = 0; jj < ny; jj++)
         for (int ii = 0; ii < nx; ii++)
@@ -377,13 +413,14 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.vw = H->vel + 2 * (size_t)nvp;
     P.viu = H->veli;
     P.viv = H->veli + nvp;
+    P.vref = H->vref;
     H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
     if (H->upd_lds > 160 * 1024) {
         free_case(H);
         return HB_EINVAL;
     }
     {
-        const int rcl = update_lds_attr(NT, H->upd_lds);
+        const int rcl = update_lds_attr(H->precision, NT, H->upd_lds);
         if (rcl != HB_OK) {
             free_case(H);
             return rcl;
@@ -392,11 +429,20 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->cur = 0;
     H->step = 0;
     const long tot = (long)nel;
-    hipLaunchKernelGGL(hb::k_init, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P, H->h[0], H->b[0], H->W[0]);
-    hipLaunchKernelGGL(hb::k_init, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P, H->h[1], H->b[1], H->W[1]);
+    hipLaunchKernelGGL(hb::k_vref, dim3((nvp + 255) / 256), dim3(256), 0, H->stream, P, H->vref);
+    for (int s = 0; s < 2; s++) {
+        if (H->precision == HB_MIXED)
+            hipLaunchKernelGGL(hb::k_init<float>, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P,
+                               (float *)H->h[s], (float *)H->b[s], H->W[s]);
+        else
+            hipLaunchKernelGGL(hb::k_init<double>, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P,
+                               (double *)H->h[s], (double *)H->b[s], H->W[s]);
+    }
     hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[0], H->dt[0]);
     HIPOK(hipGetLastError());
     HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    H->vref_host.resize(nvp);
+    HIPOK(hipMemcpy(H->vref_host.data(), H->vref, nvp * sizeof(double), hipMemcpyDeviceToHost));
     H->has_case = true;
     return HB_OK;
 }
@@ -426,13 +472,14 @@ int hb_ugks_pseudo_step(hb_handle H, int nsteps)
             H->tused += NKERN + 1;
             HIPOK(hipEventRecord(ev[0], H->stream));
         }
-        hipLaunchKernelGGL(hb::k_moments, dim3(P.nc), dim3(256), 0, H->stream, P, H->h[c], H->b[c], H->feed);
+        launch_moments(H, P, c);
         if (ev) HIPOK(hipEventRecord(ev[1], H->stream));
         hipLaunchKernelGGL(hb::k_faces, dim3((nfaces * NT + 127) / 128), dim3(128), 0, H->stream, P, H->feed, H->W[c],
                            H->dt[c], H->recx, H->recy);
         if (ev) HIPOK(hipEventRecord(ev[2], H->stream));
         hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
-                           H->W[c], H->dt[c], H->W[x], H->crec, H->dt[x], H->rpart);
+                           H->W[c], H->dt[c], H->W[x], H->crec, H->rpart);
+        hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
         if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
         hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
                            slot, H->flag);
@@ -505,15 +552,22 @@ int hb_ugks_state_out(hb_handle H, double *W, double *hh, double *bb, size_t cap
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
     if (W) HIPOK(hipMemcpy(W, H->W[H->cur], ncn * 4 * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<double> tmp;
-    double *src[2] = {H->h[H->cur], H->b[H->cur]};
+    const bool mixed = H->precision == HB_MIXED;
+    const size_t eb = elem_bytes(H);
+    std::vector<unsigned char> tmp;
+    void *src[2] = {H->h[H->cur], H->b[H->cur]};
     double *dst[2] = {hh, bb};
     for (int s = 0; s < 2; s++) {
         if (!dst[s]) continue;
-        tmp.resize(ncn * P.nvp);
-        HIPOK(hipMemcpy(tmp.data(), src[s], tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        tmp.resize(ncn * P.nvp * eb);
+        HIPOK(hipMemcpy(tmp.data(), src[s], tmp.size(), hipMemcpyDeviceToHost));
+        const double fac = s == 0 ? 1.0 : 0.5 * P.K;
         for (size_t e = 0; e < ncn; e++)
-            for (size_t a = 0; a < nv; a++) dst[s][e * nv + a] = tmp[e * P.nvp + H->perm[a]];
+            for (size_t a = 0; a < nv; a++) {
+                const size_t k = e * P.nvp + H->perm[a];
+                dst[s][e * nv + a] = mixed ? (double)((const float *)tmp.data())[k] + fac * H->vref_host[H->perm[a]]
+                                           : ((const double *)tmp.data())[k];
+            }
     }
     return HB_OK;
 }
@@ -527,15 +581,24 @@ int hb_ugks_state_in(hb_handle H, const double *W, const double *hh, const doubl
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
     if (W) HIPOK(hipMemcpy(H->W[H->cur], W, ncn * 4 * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<double> tmp;
-    double *dst[2] = {H->h[H->cur], H->b[H->cur]};
+    const bool mixed = H->precision == HB_MIXED;
+    const size_t eb = elem_bytes(H);
+    std::vector<unsigned char> tmp;
+    void *dst[2] = {H->h[H->cur], H->b[H->cur]};
     const double *src[2] = {hh, bb};
     for (int s = 0; s < 2; s++) {
         if (!src[s]) continue;
-        tmp.assign(ncn * P.nvp, 0.0);
+        tmp.assign(ncn * P.nvp * eb, 0);
+        const double fac = s == 0 ? 1.0 : 0.5 * P.K;
         for (size_t e = 0; e < ncn; e++)
-            for (size_t a = 0; a < nv; a++) tmp[e * P.nvp + H->perm[a]] = src[s][e * nv + a];
-        HIPOK(hipMemcpy(dst[s], tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+            for (size_t a = 0; a < nv; a++) {
+                const size_t k = e * P.nvp + H->perm[a];
+                if (mixed)
+                    ((float *)tmp.data())[k] = (float)(src[s][e * nv + a] - fac * H->vref_host[H->perm[a]]);
+                else
+                    ((double *)tmp.data())[k] = src[s][e * nv + a];
+            }
+        HIPOK(hipMemcpy(dst[s], tmp.data(), tmp.size(), hipMemcpyHostToDevice));
     }
     if (W) {
         hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[H->cur], H->dt[H->cur]);
@@ -564,7 +627,12 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
         return HB_ENOMEM;
     }
     const int c = H->cur;
-    hipLaunchKernelGGL(hb::k_harm_vars, dim3(P.nc), dim3(256), 0, H->stream, P, H->h[c], H->b[c], H->W[c], vars);
+    if (H->precision == HB_MIXED)
+        hipLaunchKernelGGL(hb::k_harm_vars<float>, dim3(P.nc), dim3(256), 0, H->stream, P, (const float *)H->h[c],
+                           (const float *)H->b[c], H->W[c], vars);
+    else
+        hipLaunchKernelGGL(hb::k_harm_vars<double>, dim3(P.nc), dim3(256), 0, H->stream, P, (const double *)H->h[c],
+                           (const double *)H->b[c], H->W[c], vars);
     hipLaunchKernelGGL(hb::k_harm_dft, dim3((nout + 255) / 256), dim3(256), 0, H->stream, P, vars, dre, dim_);
     int rc = HB_OK;
     if (hipGetLastError() != hipSuccess) rc = HB_EDEVICE;
