@@ -7,7 +7,7 @@ HBM.  value = cell x velocity x level updates per second.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
-                  [--precision fp64|mixed] [--no-extra] [--copy-mib N]
+                  [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -24,10 +24,50 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell·ξ·instance updates/s per pseudo-step (%HBM peak); cases/h; p50/p99"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_amd/csrc/hb_device.h",
+                  "paper_2605_03479_amd/csrc/hb_layout.h")
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
+# (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
+MEASURED_TRAFFIC = {
+    "sources_sha256_16": "a0c0c2492bdf815d",
+    "bytes": {
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 608406217,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 1059849812,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 166544138,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 2072733056,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 3855919241,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 857305532,
+    },
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def roofline(kernel, timing, algo, traffic):
+    """Roofline object of one kernel from its HIP-event timing (launches, ms)."""
+    n, ms = timing
+    avg_s = ms / max(n, 1) * 1e-3
+    achieved = None if algo is None else algo / avg_s / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": None if achieved is None else round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo}
+
+
+def traffic_bytes(workload, precision, kernel):
+    """Bytes per launch beyond L2 (FETCH_SIZE, WRITE_SIZE, calibrated on a plain
+    copy), as measured on the kernel sources whose digest is recorded; None when
+    the sources have changed since or no measurement exists."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != MEASURED_TRAFFIC["sources_sha256_16"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"].get(f"{workload}/{precision}/{kernel}")
 
 
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
@@ -61,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
+                    help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
@@ -99,7 +141,8 @@ def main():
         del src, dst
 
     prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
-    case = hbcases.shear_cavity(args.kn, args.st)
+    case = hbcases.shear_cavity(args.kn, args.st) if args.workload == "shear" else \
+        hbcases.thermal_cavity(args.kn, args.st)
     log(f"case {case.name}: {case.nc} cells x {case.nv} velocities x {case.NT} levels = {case.updates} updates/step")
     ms_step, kt, res = timed_run(hb, case, prec, stream, sync, args.steps, args.warmup)
     ups = case.updates / (ms_step * 1e-3)
@@ -108,21 +151,15 @@ def main():
         log(f"  kernel {k:9s} launches {n:6d}  avg {ms / max(n, 1) * 1e3:9.2f} us")
 
     # roofline of the dominant kernel: algorithmic HBM bytes per launch
-    #   update : read h, b and write h, b once per (cell, velocity, level) -> 4 x 8 B
-    #   moments: read h, b once -> 2 x 8 B
+    #   update_int/_bnd: read h, b and write h, b once per (cell, velocity, level) of its cells -> 4 words
+    #   moments: read h, b once per (cell, velocity, level) -> 2 words
     wb = 4.0 if prec == hb.HB_MIXED else 8.0  # bytes per stored word of h or b
-    algo_bytes = {"update": 4 * wb * case.updates, "moments": 2 * wb * case.updates}
+    n_int = max(case.nx - 4, 0) * max(case.ny - 4, 0)
+    per_cell = case.nv * case.NT
+    algo_bytes = {"update_int": 4 * wb * n_int * per_cell, "update_bnd": 4 * wb * (case.nc - n_int) * per_cell,
+                  "moments": 2 * wb * case.updates}
     dom = max(kt, key=lambda k: kt[k][1])
-    n_dom, ms_dom = kt[dom]
-    avg_s = ms_dom / n_dom * 1e-3
-    if dom in algo_bytes:
-        achieved = algo_bytes[dom] / avg_s / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo_bytes[dom]}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2)}
+    roof = roofline(dom, kt[dom], algo_bytes.get(dom), traffic_bytes(case.name, args.precision, dom))
     step_bytes = 6 * wb * case.updates  # moments (2 words) + update (4 words) per update
     kernels = {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt.items()}
 
@@ -150,14 +187,19 @@ def main():
         others = []
         if prec == hb.HB_FP64:
             others.append((case, hb.HB_MIXED, "mixed"))
-        th = hbcases.thermal_cavity(1.0, 1.0)
-        others.append((th, hb.HB_MIXED, "mixed"))
+        if args.workload == "shear":
+            others.append((hbcases.thermal_cavity(1.0, 1.0), hb.HB_MIXED, "mixed"))
         for c2, p2, pname in others:
             steps2 = max(10, min(args.steps, 60))
             ms2, kt2, _ = timed_run(hb, c2, p2, stream, sync, steps2, 5)
+            n2 = max(c2.nx - 4, 0) * max(c2.ny - 4, 0)
+            d2 = max(kt2, key=lambda k: kt2[k][1])
+            wb2 = 4.0 if p2 == hb.HB_MIXED else 8.0
+            a2 = {"update_int": 4 * wb2 * n2 * c2.nv * c2.NT, "moments": 2 * wb2 * c2.updates}.get(d2)
             extra.append({"workload": c2.name, "precision": pname, "updates_per_s": c2.updates / (ms2 * 1e-3),
                           "ms_per_step": ms2, "steps": steps2,
-                          "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt2.items()}})
+                          "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt2.items()},
+                          "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
 
     out = {

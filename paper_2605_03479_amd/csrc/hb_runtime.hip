@@ -20,8 +20,8 @@
 namespace {
 
 constexpr int RING = 1024;
-constexpr int NKERN = 5;
-const char *KNAMES[NKERN] = {"moments", "faces", "cells", "residual", "update"};
+constexpr int NKERN = 7;
+const char *KNAMES[NKERN] = {"moments", "faces", "cells", "local_dt", "residual", "update_int", "update_bnd"};
 
 struct Buf {
     void *p = nullptr;
@@ -121,35 +121,37 @@ static int update_lds_attr(int precision, int NT, size_t bytes)
 }
 
 template <int NT, typename TS>
-static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x)
+static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x, hipEvent_t mid)
 {
     const TS *h = (const TS *)H->h[c], *b = (const TS *)H->b[c];
     TS *hn = (TS *)H->h[x], *bn = (TS *)H->b[x];
     if (H->n_int > 0)
         hipLaunchKernelGGL((hb::k_update_int<NT, TS>), dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, h, b,
                            H->recx, H->recy, H->crec, H->dt[c], hn, bn);
+    if (mid) (void)hipEventRecord(mid, H->stream);
     if (H->n_bnd > 0)
         hipLaunchKernelGGL((hb::k_update_bnd<NT, TS>), dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P,
                            H->bnd_cells, h, b, H->recx, H->recy, H->crec, H->dt[c], hn, bn);
 }
 
 template <typename TS>
-static void launch_update_p(hb_ugks *H, const hb::Params &P, int c, int x)
+static void launch_update_p(hb_ugks *H, const hb::Params &P, int c, int x, hipEvent_t mid)
 {
     switch (P.NT) {
-    case 1: launch_update_t<1, TS>(H, P, c, x); break;
-    case 3: launch_update_t<3, TS>(H, P, c, x); break;
-    case 5: launch_update_t<5, TS>(H, P, c, x); break;
-    case 7: launch_update_t<7, TS>(H, P, c, x); break;
-    case 9: launch_update_t<9, TS>(H, P, c, x); break;
-    default: launch_update_t<11, TS>(H, P, c, x); break;
+    case 1: launch_update_t<1, TS>(H, P, c, x, mid); break;
+    case 3: launch_update_t<3, TS>(H, P, c, x, mid); break;
+    case 5: launch_update_t<5, TS>(H, P, c, x, mid); break;
+    case 7: launch_update_t<7, TS>(H, P, c, x, mid); break;
+    case 9: launch_update_t<9, TS>(H, P, c, x, mid); break;
+    default: launch_update_t<11, TS>(H, P, c, x, mid); break;
     }
 }
 
-static void launch_update(hb_ugks *H, const hb::Params &P, int c, int x)
+// interior then boundary-ring update; `mid` (may be null) is recorded between them
+static void launch_update(hb_ugks *H, const hb::Params &P, int c, int x, hipEvent_t mid)
 {
-    if (H->precision == HB_MIXED) launch_update_p<float>(H, P, c, x);
-    else launch_update_p<double>(H, P, c, x);
+    if (H->precision == HB_MIXED) launch_update_p<float>(H, P, c, x, mid);
+    else launch_update_p<double>(H, P, c, x, mid);
 }
 
 static void launch_moments(hb_ugks *H, const hb::Params &P, int c)
@@ -479,13 +481,14 @@ int hb_ugks_pseudo_step(hb_handle H, int nsteps)
         if (ev) HIPOK(hipEventRecord(ev[2], H->stream));
         hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
                            H->W[c], H->dt[c], H->W[x], H->crec, H->rpart);
-        hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
         if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
+        hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
+        if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
         hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
                            slot, H->flag);
-        if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
-        launch_update(H, P, c, x);
         if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
+        launch_update(H, P, c, x, ev ? ev[6] : nullptr);
+        if (ev) HIPOK(hipEventRecord(ev[7], H->stream));
         HIPOK(hipGetLastError());
         H->cur = x;
         H->step++;
