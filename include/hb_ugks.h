@@ -152,6 +152,73 @@ int hb_ugks_kernel_times(hb_handle h, const char **names, long *launches, double
 void hb_ugks_destroy(hb_handle h);
 const char *hb_ugks_strerror(int status);
 
+/* ------------------------------------------------------------------ batched form
+ * Many cases, each the method above (Sec. 2) on its own geometry, velocity
+ * grid, N_H, Kn, St and walls, advanced together.  One batch step advances
+ * every active case by one pseudo step with one kernel launch per phase of
+ * the step over all of them (moments, faces, cells, local steps, residuals;
+ * the update once per (precision, N_T) group), recorded into a HIP graph and
+ * replayed; a case's arithmetic, including its residual summation order, is
+ * that of the single-case path, so a case gives the same result alone and in a
+ * batch.  Each case is an hb_handle (queries above apply to it) whose device
+ * memory is carved from the batch's pool: admission is by device footprint.
+ * A batch is not thread-safe; its work is queued on its own stream. */
+typedef struct hb_batch *hb_batch_handle;
+
+/* Create a batch on opts->device with a device pool of pool_bytes (0: the
+ * opts->hbm_budget_bytes, else 90 % of the free device memory) and room for
+ * max_cases cases.  opts->stream NULL: the batch creates its own stream.
+ * Errors: HB_EINVAL, HB_EDEVICE, HB_ENOMEM. */
+int hb_batch_create(const hb_create_opts *opts, size_t pool_bytes, int max_cases, hb_batch_handle *out);
+
+/* Device bytes a case of this shape takes from the pool (no allocation). */
+int hb_batch_case_bytes(hb_batch_handle b, int precision, const hb_geometry *geo, int n_harmonics,
+                        const hb_vgrid *vg, size_t *bytes);
+
+/* Add a case (arguments as hb_ugks_set_case, plus its precision), reset to
+ * rest; it is active.  *case_id receives its slot.  Errors: HB_EINVAL,
+ * HB_ENOMEM (does not fit the pool now), HB_ECAPACITY (no free slot). */
+int hb_batch_add(hb_batch_handle b, int precision, const hb_geometry *geo, double Kn, double St, int n_harmonics,
+                 const hb_wall walls[4], const hb_vgrid *vg, const hb_numerics *num, int *case_id);
+
+/* Remove a case and return its memory to the pool (synchronises). */
+int hb_batch_remove(hb_batch_handle b, int case_id);
+
+/* Inactive cases keep their state and are not stepped. */
+int hb_batch_set_active(hb_batch_handle b, int case_id, int active);
+
+/* Queue nsteps batch steps (asynchronous). */
+int hb_batch_step(hb_batch_handle b, int nsteps);
+
+/* Latest residual (Eq. 43, res[4 k .. 4 k + 3]), steps taken and divergence
+ * flag of every active case k, in slot order (ids[k] = slot); any pointer may
+ * be NULL.  Synchronises.  Returns the number of active cases, or HB_ECAPACITY
+ * if capacity is below it. */
+int hb_batch_residuals(hb_batch_handle b, double *res, long *steps, int *diverged, int *ids, int capacity);
+
+/* The case's handle, brought up to date (synchronises): use it with
+ * hb_ugks_residual, hb_ugks_harmonics_out, hb_ugks_state_out/_in,
+ * hb_ugks_sizes.  hb_ugks_pseudo_step refuses it (HB_ESTATE); the batch owns
+ * and destroys it. */
+int hb_batch_case(hb_batch_handle b, int case_id, hb_handle *out);
+
+/* Time candidate launch shapes of the update and moments phases on the
+ * batch's own cases (reps launches each) and keep the fastest, remembered per
+ * (precision, N_T, padded velocity count) for later batches.  Takes one batch
+ * step first.  Errors: HB_EINVAL, HB_EDEVICE. */
+int hb_batch_tune(hb_batch_handle b, int reps);
+
+/* Chosen update shapes: per (precision, N_T) group 5 ints (precision, N_T,
+ * padded velocities, threads per block, blocks per CU; 0 = one cell per
+ * block).  Returns the number of groups or HB_ECAPACITY. */
+int hb_batch_shapes(hb_batch_handle b, int *out, int capacity);
+
+/* Replay the step from a captured graph (default) or launch it directly. */
+int hb_batch_use_graph(hb_batch_handle b, int on);
+
+int hb_batch_pool_info(hb_batch_handle b, size_t *capacity, size_t *in_use, size_t *largest_free);
+void hb_batch_destroy(hb_batch_handle b);
+
 #ifdef __cplusplus
 }
 #endif

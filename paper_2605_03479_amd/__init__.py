@@ -49,7 +49,10 @@ class hb_numerics(ctypes.Structure):
 EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
            "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
            "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
-           "hb_ugks_destroy", "hb_ugks_strerror")
+           "hb_ugks_destroy", "hb_ugks_strerror",
+           "hb_batch_create", "hb_batch_case_bytes", "hb_batch_add", "hb_batch_remove", "hb_batch_set_active",
+           "hb_batch_step", "hb_batch_residuals", "hb_batch_case", "hb_batch_tune", "hb_batch_shapes",
+           "hb_batch_use_graph", "hb_batch_pool_info", "hb_batch_destroy")
 
 _LIB = None
 
@@ -83,9 +86,27 @@ def load_library(path=None):
     L.hb_ugks_destroy.restype = None
     L.hb_ugks_strerror.argtypes = [ip]
     L.hb_ugks_strerror.restype = ctypes.c_char_p
+    szp, lp = ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_long)
+    L.hb_batch_create.argtypes = [ctypes.POINTER(hb_create_opts), sz, ip, ctypes.POINTER(vp)]
+    L.hb_batch_case_bytes.argtypes = [vp, ip, ctypes.POINTER(hb_geometry), ip, ctypes.POINTER(hb_vgrid), szp]
+    L.hb_batch_add.argtypes = [vp, ip, ctypes.POINTER(hb_geometry), dp, dp, ip, ctypes.POINTER(hb_wall),
+                               ctypes.POINTER(hb_vgrid), ctypes.POINTER(hb_numerics), ctypes.POINTER(ip)]
+    L.hb_batch_remove.argtypes = [vp, ip]
+    L.hb_batch_set_active.argtypes = [vp, ip, ip]
+    L.hb_batch_step.argtypes = [vp, ip]
+    L.hb_batch_residuals.argtypes = [vp, _D, lp, ctypes.POINTER(ip), ctypes.POINTER(ip), ip]
+    L.hb_batch_case.argtypes = [vp, ip, ctypes.POINTER(vp)]
+    L.hb_batch_tune.argtypes = [vp, ip]
+    L.hb_batch_shapes.argtypes = [vp, ctypes.POINTER(ip), ip]
+    L.hb_batch_use_graph.argtypes = [vp, ip]
+    L.hb_batch_pool_info.argtypes = [vp, szp, szp, szp]
+    L.hb_batch_destroy.argtypes = [vp]
+    L.hb_batch_destroy.restype = None
     for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_residual",
                  "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
-                 "hb_ugks_enable_timing", "hb_ugks_kernel_times"):
+                 "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
+                 "hb_batch_add", "hb_batch_remove", "hb_batch_set_active", "hb_batch_step", "hb_batch_residuals",
+                 "hb_batch_case", "hb_batch_tune", "hb_batch_shapes", "hb_batch_use_graph", "hb_batch_pool_info"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _LIB = L
@@ -123,8 +144,8 @@ def default_numerics():
     return n
 
 
-def hb_ugks_set_case(h, case):
-    """case: an object with the fields of hbcases.Case."""
+def _case_args(case):
+    """(geometry, walls, vgrid, numerics, keep-alive arrays) of an hbcases.Case."""
     xf = None if case.x_faces is None else np.ascontiguousarray(case.x_faces, np.float64)
     yf = None if case.y_faces is None else np.ascontiguousarray(case.y_faces, np.float64)
     g = hb_geometry(case.L, case.H, case.nx, case.ny, _dp(xf), _dp(yf))
@@ -132,6 +153,12 @@ def hb_ugks_set_case(h, case):
     vg = hb_vgrid(case.M, case.umax)
     nm = hb_numerics(case.cfl, case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K, case.dt_mode,
                      case.dt_fixed)
+    return g, walls, vg, nm, (xf, yf)
+
+
+def hb_ugks_set_case(h, case):
+    """case: an object with the fields of hbcases.Case."""
+    g, walls, vg, nm, keep = _case_args(case)
     return _check(load_library().hb_ugks_set_case(h, ctypes.byref(g), case.Kn, case.St, case.NH, walls,
                                                    ctypes.byref(vg), ctypes.byref(nm)), "hb_ugks_set_case")
 
@@ -253,3 +280,156 @@ class Solver:
 
     def device_bytes(self):
         return hb_ugks_device_bytes(self.h)
+
+
+# ------------------------------------------------------------- batched form
+def hb_batch_create(device=0, stream=None, pool_bytes=0, max_cases=64, hbm_budget_bytes=0):
+    o = hb_create_opts(device, stream, HB_FP64, hbm_budget_bytes)
+    b = ctypes.c_void_p()
+    _check(load_library().hb_batch_create(ctypes.byref(o), pool_bytes, max_cases, ctypes.byref(b)),
+           "hb_batch_create")
+    return b
+
+
+def hb_batch_case_bytes(b, case, precision=HB_FP64):
+    g, walls, vg, nm, keep = _case_args(case)
+    n = ctypes.c_size_t()
+    _check(load_library().hb_batch_case_bytes(b, precision, ctypes.byref(g), case.NH, ctypes.byref(vg),
+                                              ctypes.byref(n)), "hb_batch_case_bytes")
+    return n.value
+
+
+def hb_batch_add(b, case, precision=HB_FP64):
+    """Returns the slot, or raises HBError (HB_ENOMEM: does not fit the pool now)."""
+    g, walls, vg, nm, keep = _case_args(case)
+    cid = ctypes.c_int()
+    _check(load_library().hb_batch_add(b, precision, ctypes.byref(g), case.Kn, case.St, case.NH, walls,
+                                       ctypes.byref(vg), ctypes.byref(nm), ctypes.byref(cid)), "hb_batch_add")
+    return cid.value
+
+
+def hb_batch_remove(b, cid):
+    return _check(load_library().hb_batch_remove(b, int(cid)), "hb_batch_remove")
+
+
+def hb_batch_set_active(b, cid, on):
+    return _check(load_library().hb_batch_set_active(b, int(cid), int(on)), "hb_batch_set_active")
+
+
+def hb_batch_step(b, nsteps):
+    return _check(load_library().hb_batch_step(b, int(nsteps)), "hb_batch_step")
+
+
+def hb_batch_residuals(b, capacity=4096):
+    """{slot: (residual[4], steps, diverged)} of the active cases."""
+    res = np.zeros((capacity, 4))
+    steps = (ctypes.c_long * capacity)()
+    div = (ctypes.c_int * capacity)()
+    ids = (ctypes.c_int * capacity)()
+    n = _check(load_library().hb_batch_residuals(b, _dp(res), steps, div, ids, capacity), "hb_batch_residuals")
+    return {ids[k]: (res[k].copy(), steps[k], bool(div[k])) for k in range(n)}
+
+
+def hb_batch_case(b, cid):
+    h = ctypes.c_void_p()
+    _check(load_library().hb_batch_case(b, int(cid), ctypes.byref(h)), "hb_batch_case")
+    return h
+
+
+def hb_batch_tune(b, reps=3):
+    return _check(load_library().hb_batch_tune(b, int(reps)), "hb_batch_tune")
+
+
+def hb_batch_shapes(b):
+    out = (ctypes.c_int * 5 * 64)()
+    n = _check(load_library().hb_batch_shapes(b, ctypes.cast(out, ctypes.POINTER(ctypes.c_int)), 5 * 64),
+               "hb_batch_shapes")
+    flat = ctypes.cast(out, ctypes.POINTER(ctypes.c_int))
+    return [dict(precision=flat[5 * k], NT=flat[5 * k + 1], nvp=flat[5 * k + 2], threads=flat[5 * k + 3],
+                 blocks_per_cu=flat[5 * k + 4]) for k in range(n)]
+
+
+def hb_batch_use_graph(b, on):
+    return _check(load_library().hb_batch_use_graph(b, int(on)), "hb_batch_use_graph")
+
+
+def hb_batch_pool_info(b):
+    c, u, f = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().hb_batch_pool_info(b, ctypes.byref(c), ctypes.byref(u), ctypes.byref(f)),
+           "hb_batch_pool_info")
+    return c.value, u.value, f.value
+
+
+def hb_batch_destroy(b):
+    load_library().hb_batch_destroy(b)
+
+
+class BatchCase:
+    """Queries on one case of a batch (the batch owns and steps it)."""
+
+    def __init__(self, batch, cid):
+        self.batch, self.cid = batch, cid
+
+    def _h(self):
+        return hb_batch_case(self.batch.b, self.cid)
+
+    def residual(self):
+        rc, r, k = hb_ugks_residual(self._h())
+        _check(rc, "hb_ugks_residual")
+        return r
+
+    def step_index(self):
+        return hb_ugks_residual(self._h())[2]
+
+    def state(self):
+        return hb_ugks_state_out(self._h())
+
+    def set_state(self, W, h, b):
+        hb_ugks_state_in(self._h(), W, h, b)
+
+    def harmonics(self, var_mask=0x7F):
+        return hb_ugks_harmonics_out(self._h(), var_mask)
+
+
+class Batch:
+    """Many cases on one GPU, stepped together (see the batched section of hb_ugks.h)."""
+
+    def __init__(self, device=0, stream=None, pool_bytes=0, max_cases=64, hbm_budget_bytes=0):
+        self.b = hb_batch_create(device, stream, pool_bytes, max_cases, hbm_budget_bytes)
+
+    def close(self):
+        if getattr(self, "b", None):
+            hb_batch_destroy(self.b)
+            self.b = None
+
+    __del__ = close
+
+    def case_bytes(self, case, precision=HB_FP64):
+        return hb_batch_case_bytes(self.b, case, precision)
+
+    def add(self, case, precision=HB_FP64):
+        return BatchCase(self, hb_batch_add(self.b, case, precision))
+
+    def remove(self, bc):
+        hb_batch_remove(self.b, bc.cid)
+
+    def set_active(self, bc, on):
+        hb_batch_set_active(self.b, bc.cid, on)
+
+    def step(self, n=1):
+        hb_batch_step(self.b, n)
+
+    def residuals(self):
+        return hb_batch_residuals(self.b)
+
+    def tune(self, reps=3):
+        hb_batch_tune(self.b, reps)
+
+    def shapes(self):
+        return hb_batch_shapes(self.b)
+
+    def use_graph(self, on):
+        hb_batch_use_graph(self.b, on)
+
+    def pool_info(self):
+        return hb_batch_pool_info(self.b)

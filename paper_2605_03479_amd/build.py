@@ -4,8 +4,9 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "hb_runtime.hip")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("hb_runtime.hip", "hb_kernels.h", "hb_device.h", "hb_layout.h")] + [
+SRCS = [os.path.join(HERE, "csrc", "hb_lib.hip")]
+DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in ("hb_runtime.hip", "hb_batch.hip")] + [os.path.join(HERE, "csrc", f) for f in ("hb_kernels.h", "hb_batch_kernels.h", "hb_handle.h",
+                                                       "hb_device.h", "hb_layout.h")] + [
     os.path.join(ROOT, "include", "hb_ugks.h")]
 LIB = os.path.join(HERE, "libhbugks.so")
 
@@ -17,7 +18,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", LIB + ".tmp", SRC]
+           "-o", LIB + ".tmp", *SRCS]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -10,6 +10,7 @@
 //   recx [x-face][level][REC], recy [y-face][level][REC]  face records
 //   crec [cell][level][CREC]   equilibria of W^k and W^{k+1} for the collision
 // Kernels per step: moments -> faces -> cells -> residual -> update.
+#pragma once
 #include "hb_device.h"
 #include "hb_layout.h"
 
@@ -79,12 +80,11 @@ __device__ inline double slope3(double fm, double fc, double fp, int i, int len,
 // combine into the per-face feeds.
 #define K1_ROW 66
 template <typename TS>
-__global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
-                                                 double *__restrict__ feed)
+__device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                    double *__restrict__ feed, int c)
 {
     __shared__ double red[4][28 * K1_ROW];
     __shared__ double wsum[4][NMOM];
-    const int c = xcd_cell(blockIdx.x, gridDim.x);
     const int i = c % P.nx, j = c / P.nx;
     const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int NT = P.NT;
@@ -192,6 +192,13 @@ __global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict_
     }
 }
 
+template <typename TS>
+__global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                                 double *__restrict__ feed)
+{
+    moments_cell<TS>(P, h, b, feed, xcd_cell(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------- K2: faces
 // Face-frame raw moments -> W0, primitives, heat flux.
 struct FaceState {
@@ -263,14 +270,13 @@ __device__ inline void store_side(double *rec, int side, double lam, double Un, 
     s[24] = c5;
 }
 
-// one thread per (face, level); x-faces first, then y-faces
-__global__ __launch_bounds__(128) void k_faces(Params P, const double *__restrict__ feed,
-                                               const double *__restrict__ W, const double *__restrict__ dtc,
-                                               double *__restrict__ recx, double *__restrict__ recy)
+// one (face, level) per thread t; x-faces first, then y-faces
+__device__ inline void faces_thread(const Params &P, const double *__restrict__ feed, const double *__restrict__ W,
+                                    const double *__restrict__ dtc, double *__restrict__ recx,
+                                    double *__restrict__ recy, int t)
 {
     const int NT = P.NT, nx = P.nx, ny = P.ny, K = P.K;
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (nfx + nfy) * NT) return;
     const int n = t % NT;
     int f = t / NT;
@@ -490,6 +496,14 @@ __global__ __launch_bounds__(128) void k_faces(Params P, const double *__restric
     }
 }
 
+// one thread per (face, level); x-faces first, then y-faces
+__global__ __launch_bounds__(128) void k_faces(Params P, const double *__restrict__ feed,
+                                               const double *__restrict__ W, const double *__restrict__ dtc,
+                                               double *__restrict__ recx, double *__restrict__ recy)
+{
+    faces_thread(P, feed, W, dtc, recx, recy, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------- K3: cells
 __device__ inline void heat_flux_raw(const double *m, const double *mb, double U, double V, double q[2])
 {
@@ -535,14 +549,15 @@ __device__ inline void cell_eq(const Params &P, const double *Wc, const double *
 
 // one thread per (cell, level): macro update (Eq. 29), collision records, and
 // the level-0 residual terms (per-block partial sums, fixed order)
-__global__ __launch_bounds__(128) void k_cells(Params P, const double *__restrict__ feed, const double *__restrict__ recx,
-                                               const double *__restrict__ recy, const double *__restrict__ Wk,
-                                               const double *__restrict__ dtc, double *__restrict__ Wn,
-                                               double *__restrict__ crec, double *__restrict__ rpart)
+// (block blk of 128 threads within the case)
+__device__ inline void cells_block(const Params &P, const double *__restrict__ feed, const double *__restrict__ recx,
+                                   const double *__restrict__ recy, const double *__restrict__ Wk,
+                                   const double *__restrict__ dtc, double *__restrict__ Wn, double *__restrict__ crec,
+                                   double *__restrict__ rpart, int blk)
 {
     __shared__ double red[4][128];
     const int NT = P.NT, nx = P.nx;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk * 128 + threadIdx.x;
     double d2[4] = {0, 0, 0, 0};
     if (t < P.nc * NT) {
         const int c = t / NT, n = t % NT;
@@ -580,12 +595,20 @@ __global__ __launch_bounds__(128) void k_cells(Params P, const double *__restric
             for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x < 4) rpart[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 4) rpart[blk * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(128) void k_cells(Params P, const double *__restrict__ feed, const double *__restrict__ recx,
+                                               const double *__restrict__ recy, const double *__restrict__ Wk,
+                                               const double *__restrict__ dtc, double *__restrict__ Wn,
+                                               double *__restrict__ crec, double *__restrict__ rpart)
+{
+    cells_block(P, feed, recx, recy, Wk, dtc, Wn, crec, rpart, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- K4: residual
-__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
-                                               int slot, int *__restrict__ flag)
+__device__ inline void resid_block(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
+                                   int slot, int *__restrict__ flag)
 {
     __shared__ double red[4][256];
     double s[4] = {0, 0, 0, 0};
@@ -603,6 +626,12 @@ __global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart,
         ring[slot * 4 + threadIdx.x] = r;
         if (!isfinite(r)) atomicOr(flag, 1);
     }
+}
+
+__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
+                                               int slot, int *__restrict__ flag)
+{
+    resid_block(rpart, nblk, nc, ring, slot, flag);
 }
 
 // ---------------------------------------------------------------- K5: update
@@ -705,20 +734,17 @@ __device__ inline void collide_store(const Params &P, const double *cr, const do
 
 // Interior cells (2 <= i <= nx-3, 2 <= j <= ny-3): every stencil value exists
 // and every slope is limited, so the per-velocity work is straight-line code.
-template <int NT, typename TS>
 #ifndef HB_UPD_MINBLK
 #define HB_UPD_MINBLK 2
 #endif
-__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const TS *__restrict__ h,
-                                                       const TS *__restrict__ b, const double *__restrict__ recx,
-                                                       const double *__restrict__ recy,
-                                                       const double *__restrict__ crec,
-                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
-                                                       TS *__restrict__ bn)
+template <int NT, typename TS>
+__device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                       const double *__restrict__ crec, const double *__restrict__ dtc,
+                                       TS *__restrict__ hn, TS *__restrict__ bn, int ci)
 {
     extern __shared__ double tab[];
     const int nxi = P.nx - 4;
-    const int ci = xcd_cell(blockIdx.x, gridDim.x);
     const int i = 2 + ci % nxi, j = 2 + ci / nxi;
     const int M = P.M, nx = P.nx;
     const int c = j * nx + i;
@@ -809,18 +835,26 @@ __global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, con
     }
 }
 
-// Cells within two of a wall (listed in cells[]): the general stencil with
-// one-sided wall slopes and the diffuse-wall inflow.
 template <int NT, typename TS>
-__global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
-                                                       const TS *__restrict__ h, const TS *__restrict__ b,
-                                                       const double *__restrict__ recx, const double *__restrict__ recy,
+__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const TS *__restrict__ h,
+                                                       const TS *__restrict__ b, const double *__restrict__ recx,
+                                                       const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
                                                        TS *__restrict__ bn)
 {
+    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, xcd_cell(blockIdx.x, gridDim.x));
+}
+
+// Cells within two of a wall (listed in cells[]): the general stencil with
+// one-sided wall slopes and the diffuse-wall inflow.
+template <int NT, typename TS>
+__device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                       const double *__restrict__ crec, const double *__restrict__ dtc,
+                                       TS *__restrict__ hn, TS *__restrict__ bn, int c)
+{
     extern __shared__ double tab[];
-    const int c = cells[blockIdx.x];
     const int M = P.M, nx = P.nx, ny = P.ny;
     const int i = c % nx, j = c / nx;
     const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
@@ -920,6 +954,17 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
     }
 }
 
+template <int NT, typename TS>
+__global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
+                                                       const TS *__restrict__ h, const TS *__restrict__ b,
+                                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                                       const double *__restrict__ crec,
+                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
+                                                       TS *__restrict__ bn)
+{
+    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, cells[blockIdx.x]);
+}
+
 // ---------------------------------------------------------------- set-up kernels
 template <typename TS>
 __global__ void k_init(Params P, TS *h, TS *b, double *W)
@@ -957,10 +1002,14 @@ __global__ void k_vref(Params P, double *vref)
     }
 }
 
+__device__ inline void dt_thread(const Params &P, const double *W, double *dtc, int c)
+{
+    if (c < P.nc) dtc[c] = local_dt(P, W + (long)c * P.NT * 4, c % P.nx, c / P.nx);
+}
+
 __global__ void k_dt(Params P, const double *W, double *dtc)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < P.nc) dtc[c] = local_dt(P, W + (long)c * P.NT * 4, c % P.nx, c / P.nx);
+    dt_thread(P, W, dtc, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- harmonics

@@ -14,64 +14,18 @@
 #include <string>
 #include <vector>
 
-#include "hb_ugks.h"
-#include "hb_kernels.h"
+#include "hb_handle.h"
 
 namespace {
-
-constexpr int RING = 1024;
-constexpr int NKERN = 7;
-const char *KNAMES[NKERN] = {"moments", "faces", "cells", "local_dt", "residual", "update_int", "update_bnd"};
-
-struct Buf {
-    void *p = nullptr;
-    size_t n = 0;
-};
-
-}  // namespace
-
-struct hb_ugks {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int precision = HB_FP64;
-    size_t budget = 0;
-    size_t bytes = 0;
-    bool has_case = false;
-    hb::Params P{};
-    // device buffers
-    std::vector<Buf> bufs;
-    double *geo = nullptr;  // xf, yf, xc, yc, rdx, rdy, rcx, rcy, u1, w1
-    double *vel = nullptr;  // vu, vv, vw
-    int *veli = nullptr;    // viu, viv
-    void *h[2]{}, *b[2]{};  // double (FP64) or float deviations from the rest Maxwellian (mixed)
-    double *W[2]{}, *dt[2]{};
-    double *vref = nullptr;
-    std::vector<double> vref_host;
-    double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
-    int *flag = nullptr;
-    int cur = 0;
-    long step = 0;
-    int cells_blocks = 0;
-    size_t upd_lds = 0;
-    int n_int = 0, n_bnd = 0;  // interior cells (>= 2 from every wall) and the boundary ring
-    int *bnd_cells = nullptr;
-    std::vector<int> perm;  // natural alpha -> internal alpha'
-    // timing: one set of NKERN + 1 events per timed step, read back lazily
-    bool timing = false;
-    std::vector<hipEvent_t> tev;
-    size_t tused = 0;
-    double kms[NKERN]{};
-    long klaunch[NKERN]{};
-};
-
-#define HIPOK(x)                                    \
-    do {                                            \
-        if ((x) != hipSuccess) return HB_EDEVICE;   \
-    } while (0)
+const char *KNAMES[HB_NKERN] = {"moments", "faces", "cells", "local_dt", "residual", "update_int", "update_bnd"};
+}
 
 static void free_case(hb_ugks *H)
 {
-    for (auto &b : H->bufs) (void)hipFree(b.p);
+    for (auto &b : H->bufs) {
+        if (H->pool) H->pool->release(b.p);
+        else (void)hipFree(b.p);
+    }
     H->bufs.clear();
     H->bytes = 0;
     H->has_case = false;
@@ -79,8 +33,16 @@ static void free_case(hb_ugks *H)
 
 static int dalloc(hb_ugks *H, void **p, size_t nbytes)
 {
+    if (H->count_only) {
+        *p = nullptr;
+        H->bytes += HbPool::round(nbytes);
+        return HB_OK;
+    }
     if (H->budget && H->bytes + nbytes > H->budget) return HB_ENOMEM;
-    if (hipMalloc(p, nbytes) != hipSuccess) {
+    if (H->pool) {
+        *p = H->pool->take(nbytes);
+        if (!*p) return HB_ENOMEM;
+    } else if (hipMalloc(p, nbytes) != hipSuccess) {
         (void)hipGetLastError();
         return HB_ENOMEM;
     }
@@ -355,6 +317,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     const size_t nel = (size_t)P.nc * NT * nvp;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     H->cells_blocks = (P.nc * NT + 127) / 128;
+    H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
+    if (H->upd_lds > 160 * 1024) return HB_EINVAL;
     int rc = HB_OK;
 #define ALLOC(ptr, count, T)                                            \
     do {                                                                \
@@ -383,7 +347,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->recy, nfy * NT * hb::REC, double);
     ALLOC(H->crec, (size_t)P.nc * NT * hb::CREC, double);
     ALLOC(H->rpart, (size_t)H->cells_blocks * 4, double);
-    ALLOC(H->ring, (size_t)RING * 4, double);
+    ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
     ALLOC(H->vref, nvp, double);
     std::vector<int> bnd;
@@ -394,12 +358,14 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->n_int = P.nc - H->n_bnd;
     ALLOC(H->bnd_cells, bnd.size(), int);
 #undef ALLOC
+    H->bnd_host = bnd;
+    if (H->count_only) return HB_OK;
     HIPOK(hipMemcpy(H->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->veli, veli.data(), veli.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPOK(hipMemset(H->flag, 0, sizeof(int)));
     HIPOK(hipMemcpy(H->bnd_cells, bnd.data(), bnd.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPOK(hipMemset(H->ring, 0, sizeof(double) * RING * 4));
+    HIPOK(hipMemset(H->ring, 0, sizeof(double) * HB_RING * 4));
     P.xf = H->geo;
     P.yf = H->geo + (nx + 1);
     P.xc = H->geo + ox_xc;
@@ -416,11 +382,6 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.viu = H->veli;
     P.viv = H->veli + nvp;
     P.vref = H->vref;
-    H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
-    if (H->upd_lds > 160 * 1024) {
-        free_case(H);
-        return HB_EINVAL;
-    }
     {
         const int rcl = update_lds_attr(H->precision, NT, H->upd_lds);
         if (rcl != HB_OK) {
@@ -452,7 +413,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
 int hb_ugks_pseudo_step(hb_handle H, int nsteps)
 {
     if (!H) return HB_EINVAL;
-    if (!H->has_case) return HB_ESTATE;
+    if (!H->has_case || H->batch_owned) return HB_ESTATE;
     if (nsteps < 0) return HB_EINVAL;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     const hb::Params &P = H->P;
@@ -460,18 +421,18 @@ int hb_ugks_pseudo_step(hb_handle H, int nsteps)
     const int nfaces = (P.nx + 1) * P.ny + P.nx * (P.ny + 1);
     for (int s = 0; s < nsteps; s++) {
         const int c = H->cur, x = 1 - c;
-        const int slot = (int)(H->step % RING);
+        const int slot = (int)(H->step % HB_RING);
         hipEvent_t *ev = nullptr;
         if (H->timing) {
-            if (H->tused + NKERN + 1 > H->tev.size()) {
-                for (int k = 0; k <= NKERN; k++) {
+            if (H->tused + HB_NKERN + 1 > H->tev.size()) {
+                for (int k = 0; k <= HB_NKERN; k++) {
                     hipEvent_t e;
                     HIPOK(hipEventCreate(&e));
                     H->tev.push_back(e);
                 }
             }
             ev = H->tev.data() + H->tused;
-            H->tused += NKERN + 1;
+            H->tused += HB_NKERN + 1;
             HIPOK(hipEventRecord(ev[0], H->stream));
         }
         launch_moments(H, P, c);
@@ -501,8 +462,8 @@ static int collect_times(hb_ugks *H)
 {
     if (!H->tused) return HB_OK;
     HIPOK(hipEventSynchronize(H->tev[H->tused - 1]));
-    for (size_t s = 0; s < H->tused; s += NKERN + 1)
-        for (int k = 0; k < NKERN; k++) {
+    for (size_t s = 0; s < H->tused; s += HB_NKERN + 1)
+        for (int k = 0; k < HB_NKERN; k++) {
             float ms = 0.f;
             HIPOK(hipEventElapsedTime(&ms, H->tev[s + k], H->tev[s + k + 1]));
             H->kms[k] += ms;
@@ -523,7 +484,7 @@ int hb_ugks_residual(hb_handle H, double out[4], long *step_index)
         for (int k = 0; k < 4; k++) out[k] = 0.0;
         return HB_OK;
     }
-    const int slot = (int)((H->step - 1) % RING);
+    const int slot = (int)((H->step - 1) % HB_RING);
     HIPOK(hipMemcpy(out, H->ring + slot * 4, 4 * sizeof(double), hipMemcpyDeviceToHost));
     int flag = 0;
     HIPOK(hipMemcpy(&flag, H->flag, sizeof(int), hipMemcpyDeviceToHost));
@@ -667,7 +628,7 @@ int hb_ugks_enable_timing(hb_handle H, int on)
     if (H->tused) HIPOK(hipEventSynchronize(H->tev[H->tused - 1]));
     H->tused = 0;
     H->timing = on != 0;
-    for (int k = 0; k < NKERN; k++) {
+    for (int k = 0; k < HB_NKERN; k++) {
         H->kms[k] = 0.0;
         H->klaunch[k] = 0;
     }
@@ -678,16 +639,16 @@ int hb_ugks_kernel_times(hb_handle H, const char **names, long *launches, double
 {
     if (!H) return HB_EINVAL;
     if (!H->has_case) return HB_ESTATE;
-    if (capacity < NKERN) return HB_ECAPACITY;
+    if (capacity < HB_NKERN) return HB_ECAPACITY;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     const int rc = collect_times(H);
     if (rc != HB_OK) return rc;
-    for (int k = 0; k < NKERN; k++) {
+    for (int k = 0; k < HB_NKERN; k++) {
         if (names) names[k] = KNAMES[k];
         if (launches) launches[k] = H->klaunch[k];
         if (ms) ms[k] = H->kms[k];
     }
-    return NKERN;
+    return HB_NKERN;
 }
 
 }  // extern "C"

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "hb_ugks.h")).read()
-    return sorted(set(re.findall(r"\b(hb_ugks_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(hb_(?:ugks|batch)_\w+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +26,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = _declared()
-    assert len(names) >= 14
+    assert len(names) >= 27
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(hb.EXPORTS)
@@ -47,6 +47,22 @@ def test_null_and_state_errors(lib):
     out = (ctypes.c_double * 4)()
     assert lib.hb_ugks_residual(None, out, None) == hb.HB_EINVAL
     lib.hb_ugks_destroy(None)  # no-op
+
+
+def test_batch_null_and_argument_errors(lib):
+    b = ctypes.c_void_p()
+    assert lib.hb_batch_create(None, 0, 0, ctypes.byref(b)) == hb.HB_EINVAL
+    assert lib.hb_batch_create(None, 0, 4, None) == hb.HB_EINVAL
+    o = hb.hb_create_opts(4096, None, 0, 0)
+    assert lib.hb_batch_create(ctypes.byref(o), 0, 4, ctypes.byref(b)) == hb.HB_EDEVICE
+    assert lib.hb_batch_step(None, 1) == hb.HB_EINVAL
+    assert lib.hb_batch_remove(None, 0) == hb.HB_EINVAL
+    assert lib.hb_batch_set_active(None, 0, 1) == hb.HB_EINVAL
+    assert lib.hb_batch_tune(None, 1) == hb.HB_EINVAL
+    assert lib.hb_batch_residuals(None, None, None, None, None, 0) == hb.HB_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.hb_batch_case(None, 0, ctypes.byref(h)) == hb.HB_EINVAL
+    lib.hb_batch_destroy(None)  # no-op
 
 
 def test_create_bad_precision_or_device(lib):
