@@ -213,6 +213,12 @@ int hb_batch_tune(hb_batch_handle b, int reps);
  * block).  Returns the number of groups or HB_ECAPACITY. */
 int hb_batch_shapes(hb_batch_handle b, int *out, int capacity);
 
+/* Device footprint per cache group (default 224 MiB): cases are packed into
+ * groups of at most this many bytes and one group's whole step runs before
+ * the next group's, so that its stencil re-reads stay in the Infinity Cache.
+ * 0 puts every case in one group. */
+int hb_batch_set_cache_bytes(hb_batch_handle b, size_t bytes);
+
 /* Replay the step from a captured graph (default) or launch it directly. */
 int hb_batch_use_graph(hb_batch_handle b, int on);
 

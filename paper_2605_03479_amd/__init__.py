@@ -52,7 +52,7 @@ EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb
            "hb_ugks_destroy", "hb_ugks_strerror",
            "hb_batch_create", "hb_batch_case_bytes", "hb_batch_add", "hb_batch_remove", "hb_batch_set_active",
            "hb_batch_step", "hb_batch_residuals", "hb_batch_case", "hb_batch_tune", "hb_batch_shapes",
-           "hb_batch_use_graph", "hb_batch_pool_info", "hb_batch_destroy")
+           "hb_batch_use_graph", "hb_batch_set_cache_bytes", "hb_batch_pool_info", "hb_batch_destroy")
 
 _LIB = None
 
@@ -99,6 +99,7 @@ def load_library(path=None):
     L.hb_batch_tune.argtypes = [vp, ip]
     L.hb_batch_shapes.argtypes = [vp, ctypes.POINTER(ip), ip]
     L.hb_batch_use_graph.argtypes = [vp, ip]
+    L.hb_batch_set_cache_bytes.argtypes = [vp, sz]
     L.hb_batch_pool_info.argtypes = [vp, szp, szp, szp]
     L.hb_batch_destroy.argtypes = [vp]
     L.hb_batch_destroy.restype = None
@@ -106,7 +107,8 @@ def load_library(path=None):
                  "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
                  "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
                  "hb_batch_add", "hb_batch_remove", "hb_batch_set_active", "hb_batch_step", "hb_batch_residuals",
-                 "hb_batch_case", "hb_batch_tune", "hb_batch_shapes", "hb_batch_use_graph", "hb_batch_pool_info"):
+                 "hb_batch_case", "hb_batch_tune", "hb_batch_shapes", "hb_batch_use_graph", "hb_batch_set_cache_bytes",
+                 "hb_batch_pool_info"):
         getattr(L, name).restype = ctypes.c_int
     if path is None:
         _LIB = L
@@ -353,6 +355,10 @@ def hb_batch_use_graph(b, on):
     return _check(load_library().hb_batch_use_graph(b, int(on)), "hb_batch_use_graph")
 
 
+def hb_batch_set_cache_bytes(b, nbytes):
+    return _check(load_library().hb_batch_set_cache_bytes(b, int(nbytes)), "hb_batch_set_cache_bytes")
+
+
 def hb_batch_pool_info(b):
     c, u, f = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     _check(load_library().hb_batch_pool_info(b, ctypes.byref(c), ctypes.byref(u), ctypes.byref(f)),
@@ -430,6 +436,9 @@ class Batch:
 
     def use_graph(self, on):
         hb_batch_use_graph(self.b, on)
+
+    def set_cache_bytes(self, nbytes):
+        hb_batch_set_cache_bytes(self.b, nbytes)
 
     def pool_info(self):
         return hb_batch_pool_info(self.b)

@@ -85,7 +85,7 @@ struct Shape {
 };
 
 struct UpdGroup {
-    int prec = HB_FP64, NT = 1;
+    int prec = HB_FP64, NT = 1, M = 0;
     int max_nvp = 0;
     size_t lds = 0;
     DevList in, bn;
@@ -152,6 +152,32 @@ void launch_group(const UpdGroup &g, const CaseDev *cs, const CaseCtl *ctl, hipS
     else launch_group_p<double>(g, cs, ctl, st, in, rg);
 }
 
+// Cases run phase by phase together.  Groups are sized so that the device
+// footprint of their cases fits the Infinity Cache, and one group's whole step
+// runs before the next group's: the stencil re-reads of the cell-per-block
+// kernels then hit the cache instead of HBM, while small cases still share
+// launches and fill the GPU.
+struct CacheGroup {
+    DevList mom[2], faces, cells, dts, resid;
+    std::vector<UpdGroup> groups;
+    Shape mom_shape[2]{{256, 0}, {256, 0}};
+    int mom_nvp[2]{0, 0};
+    size_t bytes = 0;
+
+    void free_dev()
+    {
+        for (auto &m : mom) m.free_dev();
+        faces.free_dev();
+        cells.free_dev();
+        dts.free_dev();
+        resid.free_dev();
+        for (auto &g : groups) {
+            g.in.free_dev();
+            g.bn.free_dev();
+        }
+    }
+};
+
 }  // namespace
 
 struct hb_batch {
@@ -165,11 +191,10 @@ struct hb_batch {
     std::vector<char> active;
     CaseDev *d_cs = nullptr;
     CaseCtl *d_ctl = nullptr;
-    // work lists of the current active set
-    DevList mom[2], faces, cells, dts, resid;
-    Shape mom_shape[2]{{256, 0}, {256, 0}};
-    std::vector<UpdGroup> groups;
-    std::vector<int> ids;  // active slots
+    // work lists of the current active set, per cache group
+    std::vector<CacheGroup> cgs;
+    size_t cache_bytes = 224u << 20;  // device footprint per cache group
+    std::vector<int> ids;              // active slots
     int *d_ids = nullptr;
     double *d_res = nullptr;
     long *d_steps = nullptr;
@@ -194,16 +219,8 @@ static void drop_lists(hb_batch *B)
 {
     (void)hipStreamSynchronize(B->stream);  // nothing in flight reads the lists below
     drop_graph(B);
-    for (auto &m : B->mom) m.free_dev();
-    B->faces.free_dev();
-    B->cells.free_dev();
-    B->dts.free_dev();
-    B->resid.free_dev();
-    for (auto &g : B->groups) {
-        g.in.free_dev();
-        g.bn.free_dev();
-    }
-    B->groups.clear();
+    for (auto &cg : B->cgs) cg.free_dev();
+    B->cgs.clear();
     if (B->d_ids) (void)hipFree(B->d_ids);
     if (B->d_res) (void)hipFree(B->d_res);
     if (B->d_steps) (void)hipFree(B->d_steps);
@@ -220,54 +237,57 @@ static int grid_of(const hb_batch *B, const DevList &L, int per_cu)
     return per_cu <= 0 ? (int)L.items.size() : per_cu * B->num_cu;
 }
 
-// Work lists of the active cases, in case order then the case's own order.
+// Work lists of the active cases: cases sorted by (precision, N_T, M) and
+// packed into cache groups; within a group, in case order then the case's own.
 static int build_lists(hb_batch *B)
 {
     drop_lists(B);
     B->ids.clear();
     for (int s = 0; s < B->max_cases; s++)
         if (B->cases[s] && B->active[s]) B->ids.push_back(s);
-    for (auto &m : B->mom) {
-        m.items.clear();
-        m.cost.clear();
-    }
-    for (DevList *L : {&B->faces, &B->cells, &B->dts, &B->resid}) {
-        L->items.clear();
-        L->cost.clear();
-    }
-    std::map<std::pair<int, int>, size_t> gidx;
-    for (int s : B->ids) {
+    std::vector<int> order = B->ids;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const hb_ugks *x = B->cases[a], *y = B->cases[b];
+        return std::make_tuple(x->precision, x->P.NT, x->P.M) < std::make_tuple(y->precision, y->P.NT, y->P.M);
+    });
+    for (int s : order) {
         const hb_ugks *H = B->cases[s];
+        if (B->cgs.empty() ||
+            (B->cache_bytes && B->cgs.back().bytes > 0 && B->cgs.back().bytes + H->bytes > B->cache_bytes))
+            B->cgs.emplace_back();
+        CacheGroup &cg = B->cgs.back();
+        cg.bytes += H->bytes;
         const hb::Params &P = H->P;
         const int pm = H->precision == HB_MIXED ? 1 : 0;
         const double cc = (double)P.nvp * P.NT;
+        cg.mom_nvp[pm] = std::max(cg.mom_nvp[pm], P.nvp);
         for (int c = 0; c < P.nc; c++) {
-            B->mom[pm].items.push_back({s, c});
-            B->mom[pm].cost.push_back(cc);
+            cg.mom[pm].items.push_back({s, c});
+            cg.mom[pm].cost.push_back(cc);
         }
         const int nf = ((P.nx + 1) * P.ny + P.nx * (P.ny + 1)) * P.NT;
         for (int k = 0; k < (nf + 127) / 128; k++) {
-            B->faces.items.push_back({s, k});
-            B->faces.cost.push_back(1.0);
+            cg.faces.items.push_back({s, k});
+            cg.faces.cost.push_back(1.0);
         }
         for (int k = 0; k < H->cells_blocks; k++) {
-            B->cells.items.push_back({s, k});
-            B->cells.cost.push_back(1.0);
+            cg.cells.items.push_back({s, k});
+            cg.cells.cost.push_back(1.0);
         }
         for (int k = 0; k < (P.nc + 127) / 128; k++) {
-            B->dts.items.push_back({s, k});
-            B->dts.cost.push_back(1.0);
+            cg.dts.items.push_back({s, k});
+            cg.dts.cost.push_back(1.0);
         }
-        B->resid.items.push_back({s, 0});
-        B->resid.cost.push_back((double)H->cells_blocks);
-        auto key = std::make_pair(H->precision, P.NT);
-        if (!gidx.count(key)) {
-            gidx[key] = B->groups.size();
-            B->groups.emplace_back();
-            B->groups.back().prec = H->precision;
-            B->groups.back().NT = P.NT;
+        cg.resid.items.push_back({s, 0});
+        cg.resid.cost.push_back((double)H->cells_blocks);
+        if (cg.groups.empty() || cg.groups.back().prec != H->precision || cg.groups.back().NT != P.NT ||
+            cg.groups.back().M != P.M) {
+            cg.groups.emplace_back();
+            cg.groups.back().prec = H->precision;
+            cg.groups.back().NT = P.NT;
+            cg.groups.back().M = P.M;
         }
-        UpdGroup &g = B->groups[gidx[key]];
+        UpdGroup &g = cg.groups.back();
         g.max_nvp = std::max(g.max_nvp, P.nvp);
         g.lds = std::max(g.lds, H->upd_lds);
         for (int ci = 0; ci < H->n_int; ci++) {
@@ -280,26 +300,25 @@ static int build_lists(hb_batch *B)
         }
     }
     int rc = HB_OK;
-    for (int pm = 0; pm < 2; pm++) {
-        int nvp = 0;
-        for (int s : B->ids)
-            if ((B->cases[s]->precision == HB_MIXED) == (pm == 1)) nvp = std::max(nvp, B->cases[s]->P.nvp);
-        auto t = g_tuned.find(std::make_tuple(pm ? HB_MIXED : HB_FP64, 0, nvp));
-        if (t != g_tuned.end()) B->mom_shape[pm] = t->second;
-        if ((rc = B->mom[pm].upload(grid_of(B, B->mom[pm], B->mom_shape[pm].per_cu), 256)) != HB_OK) return rc;
-    }
-    if ((rc = B->faces.upload(grid_of(B, B->faces, 0), 128)) != HB_OK) return rc;
-    if ((rc = B->cells.upload(grid_of(B, B->cells, 0), 128)) != HB_OK) return rc;
-    if ((rc = B->dts.upload(grid_of(B, B->dts, 0), 128)) != HB_OK) return rc;
-    if ((rc = B->resid.upload(grid_of(B, B->resid, 0), 256)) != HB_OK) return rc;
-    for (auto &g : B->groups) {
-        auto t = g_tuned.find(std::make_tuple(g.prec, g.NT, g.max_nvp));
-        if (t != g_tuned.end()) g.shape = t->second;
-        if (g.prec == HB_MIXED) rc = set_batch_lds_p<float>(g.NT, g.lds);
-        else rc = set_batch_lds_p<double>(g.NT, g.lds);
-        if (rc != HB_OK) return rc;
-        if ((rc = g.in.upload(grid_of(B, g.in, g.shape.per_cu), g.shape.tpb)) != HB_OK) return rc;
-        if ((rc = g.bn.upload(grid_of(B, g.bn, g.shape.per_cu), g.shape.tpb)) != HB_OK) return rc;
+    for (auto &cg : B->cgs) {
+        for (int pm = 0; pm < 2; pm++) {
+            auto t = g_tuned.find(std::make_tuple(pm ? HB_MIXED : HB_FP64, 0, cg.mom_nvp[pm]));
+            if (t != g_tuned.end()) cg.mom_shape[pm] = t->second;
+            if ((rc = cg.mom[pm].upload(grid_of(B, cg.mom[pm], cg.mom_shape[pm].per_cu), 256)) != HB_OK) return rc;
+        }
+        if ((rc = cg.faces.upload(grid_of(B, cg.faces, 0), 128)) != HB_OK) return rc;
+        if ((rc = cg.cells.upload(grid_of(B, cg.cells, 0), 128)) != HB_OK) return rc;
+        if ((rc = cg.dts.upload(grid_of(B, cg.dts, 0), 128)) != HB_OK) return rc;
+        if ((rc = cg.resid.upload(grid_of(B, cg.resid, 0), 256)) != HB_OK) return rc;
+        for (auto &g : cg.groups) {
+            auto t = g_tuned.find(std::make_tuple(g.prec, g.NT, g.max_nvp));
+            if (t != g_tuned.end()) g.shape = t->second;
+            if (g.prec == HB_MIXED) rc = set_batch_lds_p<float>(g.NT, g.lds);
+            else rc = set_batch_lds_p<double>(g.NT, g.lds);
+            if (rc != HB_OK) return rc;
+            if ((rc = g.in.upload(grid_of(B, g.in, g.shape.per_cu), g.shape.tpb)) != HB_OK) return rc;
+            if ((rc = g.bn.upload(grid_of(B, g.bn, g.shape.per_cu), g.shape.tpb)) != HB_OK) return rc;
+        }
     }
     const int n = (int)B->ids.size();
     if (n > 0) {
@@ -316,30 +335,40 @@ static int build_lists(hb_batch *B)
     return HB_OK;
 }
 
-// The launches of one batch step, in the order of the single-case step.
+static void launch_moments(const CacheGroup &cg, int pm, const CaseDev *cs, const CaseCtl *ctl, hipStream_t st)
+{
+    const DevList &L = cg.mom[pm];
+    if (!L.grid) return;
+    if (pm == 0)
+        hipLaunchKernelGGL(hb::kb_moments<double>, dim3(L.grid), dim3(256), 0, st, cs, ctl, L.d_items, L.d_bstart);
+    else
+        hipLaunchKernelGGL(hb::kb_moments<float>, dim3(L.grid), dim3(256), 0, st, cs, ctl, L.d_items, L.d_bstart);
+}
+
+// The launches of one batch step: per cache group, the phases in the order
+// of the single-case step; then the buffer swap of every stepped case.
 static void enqueue_step(hb_batch *B)
 {
     hipStream_t st = B->stream;
     const CaseDev *cs = B->d_cs;
     const CaseCtl *ctl = B->d_ctl;
-    if (B->mom[0].grid)
-        hipLaunchKernelGGL(hb::kb_moments<double>, dim3(B->mom[0].grid), dim3(256), 0, st, cs, ctl,
-                           B->mom[0].d_items, B->mom[0].d_bstart);
-    if (B->mom[1].grid)
-        hipLaunchKernelGGL(hb::kb_moments<float>, dim3(B->mom[1].grid), dim3(256), 0, st, cs, ctl, B->mom[1].d_items,
-                           B->mom[1].d_bstart);
-    if (B->faces.grid)
-        hipLaunchKernelGGL(hb::kb_faces, dim3(B->faces.grid), dim3(128), 0, st, cs, ctl, B->faces.d_items,
-                           B->faces.d_bstart);
-    if (B->cells.grid)
-        hipLaunchKernelGGL(hb::kb_cells, dim3(B->cells.grid), dim3(128), 0, st, cs, ctl, B->cells.d_items,
-                           B->cells.d_bstart);
-    if (B->dts.grid)
-        hipLaunchKernelGGL(hb::kb_dt, dim3(B->dts.grid), dim3(128), 0, st, cs, ctl, B->dts.d_items, B->dts.d_bstart);
-    if (B->resid.grid)
-        hipLaunchKernelGGL(hb::kb_resid, dim3(B->resid.grid), dim3(256), 0, st, cs, ctl, B->resid.d_items,
-                           B->resid.d_bstart);
-    for (auto &g : B->groups) launch_group(g, cs, ctl, st);
+    for (const CacheGroup &cg : B->cgs) {
+        launch_moments(cg, 0, cs, ctl, st);
+        launch_moments(cg, 1, cs, ctl, st);
+        if (cg.faces.grid)
+            hipLaunchKernelGGL(hb::kb_faces, dim3(cg.faces.grid), dim3(128), 0, st, cs, ctl, cg.faces.d_items,
+                               cg.faces.d_bstart);
+        if (cg.cells.grid)
+            hipLaunchKernelGGL(hb::kb_cells, dim3(cg.cells.grid), dim3(128), 0, st, cs, ctl, cg.cells.d_items,
+                               cg.cells.d_bstart);
+        if (cg.dts.grid)
+            hipLaunchKernelGGL(hb::kb_dt, dim3(cg.dts.grid), dim3(128), 0, st, cs, ctl, cg.dts.d_items,
+                               cg.dts.d_bstart);
+        if (cg.resid.grid)
+            hipLaunchKernelGGL(hb::kb_resid, dim3(cg.resid.grid), dim3(256), 0, st, cs, ctl, cg.resid.d_items,
+                               cg.resid.d_bstart);
+        for (auto &g : cg.groups) launch_group(g, cs, ctl, st);
+    }
     const int n = (int)B->ids.size();
     if (n) hipLaunchKernelGGL(hb::kb_step_end, dim3((n + 127) / 128), dim3(128), 0, st, B->d_ctl, B->d_ids, n);
 }
@@ -631,49 +660,45 @@ int hb_batch_tune(hb_batch_handle B, int reps)
         return ms;
     };
     const Shape upd_cands[] = {{256, 0}, {128, 0}, {64, 0}, {256, 2}, {256, 4}, {128, 4}, {128, 8}};
-    for (auto &g : B->groups) {
-        double best = 1e300;
-        Shape bs = g.shape;
-        for (const Shape &c : upd_cands) {
-            if ((rc = g.in.upload(grid_of(B, g.in, c.per_cu), c.tpb)) != HB_OK) break;
-            if ((rc = g.bn.upload(grid_of(B, g.bn, c.per_cu), c.tpb)) != HB_OK) break;
-            const double t = timeit([&] { launch_group(g, B->d_cs, B->d_ctl, B->stream); });
-            if (t < best) {
-                best = t;
-                bs = c;
+    std::map<std::tuple<int, int, int>, Shape> done;
+    for (auto &cg : B->cgs)
+        for (auto &g : cg.groups) {
+            const auto key = std::make_tuple(g.prec, g.NT, g.max_nvp);
+            if (done.count(key)) continue;
+            double best = 1e300;
+            Shape bs = g.shape;
+            for (const Shape &c : upd_cands) {
+                if ((rc = g.in.upload(grid_of(B, g.in, c.per_cu), c.tpb)) != HB_OK) break;
+                if ((rc = g.bn.upload(grid_of(B, g.bn, c.per_cu), c.tpb)) != HB_OK) break;
+                const double t = timeit([&] { launch_group(g, B->d_cs, B->d_ctl, B->stream); });
+                if (t < best) {
+                    best = t;
+                    bs = c;
+                }
             }
+            if (rc != HB_OK) break;
+            done[key] = bs;
+            g_tuned[key] = bs;
         }
-        if (rc != HB_OK) break;
-        g.shape = bs;
-        g_tuned[std::make_tuple(g.prec, g.NT, g.max_nvp)] = bs;
-    }
     const Shape mom_cands[] = {{256, 0}, {256, 2}, {256, 4}, {256, 8}};
-    for (int pm = 0; pm < 2 && rc == HB_OK; pm++) {
-        DevList &L = B->mom[pm];
-        if (L.items.empty()) continue;
-        int nvp = 0;
-        for (int s : B->ids)
-            if ((B->cases[s]->precision == HB_MIXED) == (pm == 1)) nvp = std::max(nvp, B->cases[s]->P.nvp);
-        double best = 1e300;
-        Shape bs = B->mom_shape[pm];
-        for (const Shape &c : mom_cands) {
-            if ((rc = L.upload(grid_of(B, L, c.per_cu), 256)) != HB_OK) break;
-            const double t = timeit([&] {
-                if (pm == 0)
-                    hipLaunchKernelGGL(hb::kb_moments<double>, dim3(L.grid), dim3(256), 0, B->stream, B->d_cs,
-                                       B->d_ctl, L.d_items, L.d_bstart);
-                else
-                    hipLaunchKernelGGL(hb::kb_moments<float>, dim3(L.grid), dim3(256), 0, B->stream, B->d_cs,
-                                       B->d_ctl, L.d_items, L.d_bstart);
-            });
-            if (t < best) {
-                best = t;
-                bs = c;
+    for (auto &cg : B->cgs)
+        for (int pm = 0; pm < 2 && rc == HB_OK; pm++) {
+            DevList &L = cg.mom[pm];
+            const auto key = std::make_tuple(pm ? HB_MIXED : HB_FP64, 0, cg.mom_nvp[pm]);
+            if (L.items.empty() || done.count(key)) continue;
+            double best = 1e300;
+            Shape bs = cg.mom_shape[pm];
+            for (const Shape &c : mom_cands) {
+                if ((rc = L.upload(grid_of(B, L, c.per_cu), 256)) != HB_OK) break;
+                const double t = timeit([&] { launch_moments(cg, pm, B->d_cs, B->d_ctl, B->stream); });
+                if (t < best) {
+                    best = t;
+                    bs = c;
+                }
             }
+            done[key] = bs;
+            g_tuned[key] = bs;
         }
-        B->mom_shape[pm] = bs;
-        g_tuned[std::make_tuple(pm ? HB_MIXED : HB_FP64, 0, nvp)] = bs;
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != HB_OK) return rc;
@@ -684,21 +709,33 @@ int hb_batch_tune(hb_batch_handle B, int reps)
 
 int hb_batch_shapes(hb_batch_handle B, int *out, int capacity)
 {
-    // per update group: precision, NT, max padded velocities, threads per block, blocks per CU
+    // per distinct update group: precision, NT, padded velocities, threads per block, blocks per CU
     if (!B || !out) return HB_EINVAL;
     int rc = ensure_lists(B);
     if (rc != HB_OK) return rc;
-    const int n = (int)B->groups.size();
+    std::map<std::tuple<int, int, int>, Shape> seen;
+    for (auto &cg : B->cgs)
+        for (auto &g : cg.groups) seen[std::make_tuple(g.prec, g.NT, g.max_nvp)] = g.shape;
+    const int n = (int)seen.size();
     if (capacity < 5 * n) return HB_ECAPACITY;
-    for (int k = 0; k < n; k++) {
-        const UpdGroup &g = B->groups[k];
-        out[5 * k + 0] = g.prec;
-        out[5 * k + 1] = g.NT;
-        out[5 * k + 2] = g.max_nvp;
-        out[5 * k + 3] = g.shape.tpb;
-        out[5 * k + 4] = g.shape.per_cu;
+    int k = 0;
+    for (auto &kv : seen) {
+        out[5 * k + 0] = std::get<0>(kv.first);
+        out[5 * k + 1] = std::get<1>(kv.first);
+        out[5 * k + 2] = std::get<2>(kv.first);
+        out[5 * k + 3] = kv.second.tpb;
+        out[5 * k + 4] = kv.second.per_cu;
+        k++;
     }
     return n;
+}
+
+int hb_batch_set_cache_bytes(hb_batch_handle B, size_t bytes)
+{
+    if (!B) return HB_EINVAL;
+    B->cache_bytes = bytes;
+    B->lists_valid = false;
+    return HB_OK;
 }
 
 int hb_batch_use_graph(hb_batch_handle B, int on)

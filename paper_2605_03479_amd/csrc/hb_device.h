@@ -12,8 +12,25 @@
 
 namespace hb {
 
+// Pointers typed in the global address space.  Kernel arguments are known to
+// be global, but pointers read from memory (the per-case tables of the batched
+// form) are not, and the compiler would access them with flat instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ inline gptr<T> G(T *p)
+{
+    return (gptr<T>)p;
+}
+template <class T>
+__device__ inline gptr<T> G(gptr<T> p)
+{
+    return p;
+}
+
 struct Params {
     int nx, ny, nc, M, Mh, Q, Qp, nvp, NT, NH, K, face_dt, dt_mode;
+    int ls;  // level stride of h, b in words (nvp plus padding)
     double omega, mu_ref, omega_vss, Pr, cfl, gamma, umax, dt_fixed;
     double E[HB_NTMAX * HB_NTMAX];
     double wall_ut[4][HB_NTMAX], wall_T[4][HB_NTMAX];

@@ -28,22 +28,22 @@ __device__ inline int xcd_cell(int b, int G)
 // Storage of (h, b): FP64 values, or FP32 deviations from the rest Maxwellian
 // H_ref = exp(-|u|^2)/pi (B_ref = K/2 H_ref) for the mixed form.  All
 // arithmetic below runs in FP64 either way.
-template <typename TS>
-__device__ inline double ldv(const TS *p, long off, double ref)
+template <typename TS, typename Ptr>
+__device__ inline double ldv(Ptr p, long off, double ref)
 {
-    if constexpr (sizeof(TS) == 4) return static_cast<double>(p[off]) + ref;
-    else return p[off];
+    if constexpr (sizeof(TS) == 4) return static_cast<double>(G(p)[off]) + ref;
+    else return G(p)[off];
 }
-template <typename TS>
-__device__ inline void stv(TS *p, long off, double v, double ref)
+template <typename TS, typename Ptr>
+__device__ inline void stv(Ptr p, long off, double v, double ref)
 {
-    if constexpr (sizeof(TS) == 4) p[off] = static_cast<float>(v - ref);
-    else p[off] = v;
+    if constexpr (sizeof(TS) == 4) G(p)[off] = static_cast<float>(v - ref);
+    else G(p)[off] = v;
 }
 template <typename TS>
 __device__ inline double href_of(const Params &P, int ap)
 {
-    if constexpr (sizeof(TS) == 4) return P.vref[ap];
+    if constexpr (sizeof(TS) == 4) return G(P.vref)[ap];
     else return 0.0;
 }
 
@@ -65,12 +65,24 @@ __device__ inline double vanleer_fast(double a, double b)
 }
 
 // slope at index i of a line from the values at i-1, i, i+1 (one-sided at the walls)
-__device__ inline double slope3(double fm, double fc, double fp, int i, int len, const double *__restrict__ rc)
+__device__ inline double slope3(double fm, double fc, double fp, int i, int len, const double *__restrict__ rc_)
 {
+    const gptr<const double> rc = G(rc_);
     if (i == 0) return (fp - fc) * rc[1];
     if (i == len - 1) return (fc - fm) * rc[i];
     return vanleer_fast((fc - fm) * rc[i], (fp - fc) * rc[i + 1]);
 }
+
+// The same slope from per-cell constants: mode 0 interior (limited), 1 at the
+// low wall, 2 at the high wall; rm = rc[i], rp = rc[i+1].  fm (mode 1) or fp
+// (mode 2) is not read, so the caller may pass any finite value there.
+__device__ inline double slope_c(double fm, double fc, double fp, int mode, double rm, double rp)
+{
+    if (mode == 1) return (fp - fc) * rp;
+    if (mode == 2) return (fc - fm) * rm;
+    return vanleer_fast((fc - fm) * rm, (fp - fc) * rp);
+}
+__device__ inline int wall_mode(int i, int len) { return i == 0 ? 1 : (i == len - 1 ? 2 : 0); }
 
 // ---------------------------------------------------------------- K1: moments
 // One block per cell, wave q = velocity quadrant q (u>0: bit 0, v>0: bit 1).
@@ -88,10 +100,15 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     const int i = c % P.nx, j = c / P.nx;
     const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int NT = P.NT;
-    const long sx = (long)NT * P.nvp;        // x-neighbour stride
-    const long sy = (long)P.nx * NT * P.nvp;  // y-neighbour stride
-    const double dxo = (q & 1) ? (P.xf[i + 1] - P.xc[i]) : (P.xf[i] - P.xc[i]);
-    const double dyo = (q & 2) ? (P.yf[j + 1] - P.yc[j]) : (P.yf[j] - P.yc[j]);
+    const long sx = (long)NT * P.ls;        // x-neighbour stride
+    const long sy = (long)P.nx * NT * P.ls;  // y-neighbour stride
+    const double dxo = (q & 1) ? (G(P.xf)[i + 1] - G(P.xc)[i]) : (G(P.xf)[i] - G(P.xc)[i]);
+    const double dyo = (q & 2) ? (G(P.yf)[j + 1] - G(P.yc)[j]) : (G(P.yf)[j] - G(P.yc)[j]);
+    // neighbour offsets clamped to the cell itself at the walls, so every load
+    // of the stencil is unconditional and they all issue together
+    const int mx = wall_mode(i, P.nx), my = wall_mode(j, P.ny);
+    const long oW = mx == 1 ? 0 : -sx, oE = mx == 2 ? 0 : sx, oS = my == 1 ? 0 : -sy, oN = my == 2 ? 0 : sy;
+    const double rxm = G(P.rcx)[i], rxp = G(P.rcx)[i + 1], rym = G(P.rcy)[j], ryp = G(P.rcy)[j + 1];
 
     for (int n = 0; n < NT; n++) {
         double acc[NMOM];
@@ -99,17 +116,17 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
         for (int k = 0; k < NMOM; k++) acc[k] = 0.0;
         for (int r = lane; r < P.Qp; r += 64) {
             const int ap = q * P.Qp + r;
-            const double u = P.vu[ap], v = P.vv[ap], w = P.vw[ap];
-            const long e = ((long)c * NT + n) * P.nvp + ap;
+            const double u = G(P.vu)[ap], v = G(P.vv)[ap], w = G(P.vw)[ap];
+            const long e = ((long)c * NT + n) * P.ls + ap;
             const TS *hp = h + e, *bp = b + e;
             const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
             const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
-            const double hW = i > 0 ? ldv<TS>(hp, -sx, rh) : 0.0, bW = i > 0 ? ldv<TS>(bp, -sx, rb) : 0.0;
-            const double hE = i < P.nx - 1 ? ldv<TS>(hp, sx, rh) : 0.0, bE = i < P.nx - 1 ? ldv<TS>(bp, sx, rb) : 0.0;
-            const double hS = j > 0 ? ldv<TS>(hp, -sy, rh) : 0.0, bS = j > 0 ? ldv<TS>(bp, -sy, rb) : 0.0;
-            const double hN = j < P.ny - 1 ? ldv<TS>(hp, sy, rh) : 0.0, bN = j < P.ny - 1 ? ldv<TS>(bp, sy, rb) : 0.0;
-            const double sxh = slope3(hW, hc, hE, i, P.nx, P.rcx), sxb = slope3(bW, bc, bE, i, P.nx, P.rcx);
-            const double syh = slope3(hS, hc, hN, j, P.ny, P.rcy), syb = slope3(bS, bc, bN, j, P.ny, P.rcy);
+            const double hW = ldv<TS>(hp, oW, rh), bW = ldv<TS>(bp, oW, rb);
+            const double hE = ldv<TS>(hp, oE, rh), bE = ldv<TS>(bp, oE, rb);
+            const double hS = ldv<TS>(hp, oS, rh), bS = ldv<TS>(bp, oS, rb);
+            const double hN = ldv<TS>(hp, oN, rh), bN = ldv<TS>(bp, oN, rb);
+            const double sxh = slope_c(hW, hc, hE, mx, rxm, rxp), sxb = slope_c(bW, bc, bE, mx, rxm, rxp);
+            const double syh = slope_c(hS, hc, hN, my, rym, ryp), syb = slope_c(bS, bc, bN, my, rym, ryp);
             const double uu = u * u, uv = u * v, vv = v * v;
             const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
                                    w * vv * v};
@@ -178,7 +195,7 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
         }
         __syncthreads();
         // combine quadrants: E = q1 + q3, W = q0 + q2, N = q2 + q3, S = q0 + q1
-        double *out = feed + ((long)c * NT + n) * FEED;
+        const gptr<double> out = G(feed) + ((long)c * NT + n) * FEED;
         for (int t = threadIdx.x; t < FEED; t += blockDim.x) {
             double val;
             if (t < 21) val = wsum[1][t] + wsum[3][t];
@@ -651,7 +668,8 @@ __device__ inline double p3_eval(Ptr c, double n, double t)
 // never wait behind the vector loads of the stencil.
 typedef __attribute__((address_space(4))) const double cdouble;
 
-__device__ inline cdouble *wave_uniform(const double *p)
+template <typename Ptr>
+__device__ inline cdouble *wave_uniform(Ptr p)
 {
     const unsigned long long a = reinterpret_cast<unsigned long long>(p);
     const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
@@ -672,21 +690,21 @@ __device__ inline void face_flux(Ptr s, double e, double un, double ut, double h
 // Tables of one cell's block: 4 faces x NT levels x (merged normal, two
 // tangential) + NT levels x (u, v) x (k, k+1) for the cell equilibria.
 template <int NT>
-__device__ inline void build_tables(const Params &P, const double *const fr[4], const double *cr, double *tab)
+__device__ inline void build_tables(const Params &P, const gptr<const double> fr[4], gptr<const double> cr, double *tab)
 {
     const int M = P.M, ftab = 12 * NT * M;
     for (int t = threadIdx.x; t < 16 * NT * M; t += blockDim.x) {
         const int k = t % M;
-        const double x = P.u1[k];
+        const double x = G(P.u1)[k];
         double lam, U;
         if (t < ftab) {
             const int which = (t / M) % 3, fn = t / (3 * M), n = fn % NT, fs = fn / NT;
-            const double *sd = fr[fs] + n * REC + REC_SIDE + REC_SIDEW * (which == 0 ? (x > 0.0 ? 1 : 0) : which - 1);
+            const gptr<const double> sd = fr[fs] + n * REC + REC_SIDE + REC_SIDEW * (which == 0 ? (x > 0.0 ? 1 : 0) : which - 1);
             lam = sd[0];
             U = which == 0 ? sd[1] : sd[2];
         } else {
             const int tt = t - ftab, which = (tt / M) % 4, n = tt / (4 * M);
-            const double *cc = cr + n * CREC + (which >= 2 ? CREC_T : 0);
+            const gptr<const double> cc = cr + n * CREC + (which >= 2 ? CREC_T : 0);
             lam = cc[0];
             U = (which & 1) ? cc[2] : cc[1];
         }
@@ -697,7 +715,7 @@ __device__ inline void build_tables(const Params &P, const double *const fr[4], 
 // Spectral source and semi-implicit collision (Eq. 30) for one velocity at all
 // levels, then the store of h^{k+1}, b^{k+1}.
 template <int NT, typename TS>
-__device__ inline void collide_store(const Params &P, const double *cr, const double *ctab, double dG, double u,
+__device__ inline void collide_store(const Params &P, gptr<const double> cr, const double *ctab, double dG, double u,
                                      double v, int iu, int iv, const double *hk, const double *bk, const double *dh,
                                      const double *db, TS *hn, TS *bn, long e0, double rh, double rb)
 {
@@ -711,12 +729,12 @@ __device__ inline void collide_store(const Params &P, const double *cr, const do
             Eh += P.E[n * NT + m] * hk[m];
             Eb += P.E[n * NT + m] * bk[m];
         }
-        const double *cc = cr + n * CREC;
+        const gptr<const double> cc = cr + n * CREC;
         const double *ct = ctab + n * 4 * M;
         double heq[2], beq[2];
 #pragma unroll
         for (int s2 = 0; s2 < 2; s2++) {
-            const double *q = cc + CREC_T * s2;
+            const gptr<const double> q = cc + CREC_T * s2;
             const double lam2 = 2.0 * q[0];
             const double e = ct[(2 * s2) * M + iu] * ct[(2 * s2 + 1) * M + iv];
             const double cu = u - q[1], cv = v - q[2];
@@ -727,8 +745,8 @@ __device__ inline void collide_store(const Params &P, const double *cr, const do
         const double a0 = cc[5], a1 = cc[CREC_T + 5], rden = cc[16];
         const double hnew = (hk[n] - dG * dh[n] - dgw * Eh + a1 * heq[1] + a0 * (heq[0] - hk[n])) * rden;
         const double bnew = (bk[n] - dG * db[n] - dgw * Eb + a1 * beq[1] + a0 * (beq[0] - bk[n])) * rden;
-        stv<TS>(hn, e0 + (long)n * P.nvp, hnew, rh);
-        stv<TS>(bn, e0 + (long)n * P.nvp, bnew, rb);
+        stv<TS>(hn, e0 + (long)n * P.ls, hnew, rh);
+        stv<TS>(bn, e0 + (long)n * P.ls, bnew, rb);
     }
 }
 
@@ -748,40 +766,41 @@ __device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h
     const int i = 2 + ci % nxi, j = 2 + ci / nxi;
     const int M = P.M, nx = P.nx;
     const int c = j * nx + i;
-    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
-                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
-    const double *cr = crec + (long)c * NT * CREC;
+    const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
+                                      G(recy) + (long)(j * nx + i) * NT * REC,
+                                      G(recy) + (long)((j + 1) * nx + i) * NT * REC};
+    const gptr<const double> cr = G(crec) + (long)c * NT * CREC;
     build_tables<NT>(P, fr, cr, tab);
     __syncthreads();
     const double *ctab = tab + 12 * NT * M;
-    const long sx = (long)NT * P.nvp, sy = (long)nx * NT * P.nvp;
+    const long sx = (long)NT * P.ls, sy = (long)nx * NT * P.ls;
     const double dG = dtc[c];
-    const double rdx = P.rdx[i], rdy = P.rdy[j];
+    const double rdx = G(P.rdx)[i], rdy = G(P.rdy)[j];
     const double *rcx = P.rcx, *rcy = P.rcy;
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
         if (r >= P.Q) continue;
-        const double u = P.vu[ap], v = P.vv[ap];
-        const int iu = P.viu[ap], iv = P.viv[ap];
+        const double u = G(P.vu)[ap], v = G(P.vv)[ap];
+        const int iu = G(P.viu)[ap], iv = G(P.viv)[ap];
         const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
         const int fxo = su ? 1 : 0, fxi = 1 - fxo, fyo = sv ? 3 : 2, fyi = 5 - fyo;
         const int iU = su ? i - 1 : i + 1, jV = sv ? j - 1 : j + 1;
         const long oU = su ? -sx : sx, oV = sv ? -sy : sy;
-        const double dxo = su ? P.xf[i + 1] - P.xc[i] : P.xf[i] - P.xc[i];
-        const double dyo = sv ? P.yf[j + 1] - P.yc[j] : P.yf[j] - P.yc[j];
-        const double dxi = su ? P.xf[i] - P.xc[iU] : P.xf[i + 1] - P.xc[iU];
-        const double dyi = sv ? P.yf[j] - P.yc[jV] : P.yf[j + 1] - P.yc[jV];
+        const double dxo = su ? G(P.xf)[i + 1] - G(P.xc)[i] : G(P.xf)[i] - G(P.xc)[i];
+        const double dyo = sv ? G(P.yf)[j + 1] - G(P.yc)[j] : G(P.yf)[j] - G(P.yc)[j];
+        const double dxi = su ? G(P.xf)[i] - G(P.xc)[iU] : G(P.xf)[i + 1] - G(P.xc)[iU];
+        const double dyi = sv ? G(P.yf)[j] - G(P.yc)[jV] : G(P.yf)[j + 1] - G(P.yc)[jV];
         // limiter reciprocal centre distances: own cell and the two upwind neighbours
         const double rxm = rcx[i], rxp = rcx[i + 1], rym = rcy[j], ryp = rcy[j + 1];
         const double rUm = rcx[iU], rUp = rcx[iU + 1], rVm = rcy[jV], rVp = rcy[jV + 1];
         double hk[NT], bk[NT], dh[NT], db[NT];
-        const long e0 = (long)c * NT * P.nvp + ap;
+        const long e0 = (long)c * NT * P.ls + ap;
 #pragma unroll
         for (int n = 0; n < NT; n++) {
-            const TS *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
             const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
             const double hW = ldv<TS>(hp, -sx, rh), bW = ldv<TS>(bp, -sx, rb), hE = ldv<TS>(hp, sx, rh), bE = ldv<TS>(bp, sx, rb);
             const double hS = ldv<TS>(hp, -sy, rh), bS = ldv<TS>(bp, -sy, rb), hN = ldv<TS>(hp, sy, rh), bN = ldv<TS>(bp, sy, rb);
@@ -857,23 +876,29 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
     extern __shared__ double tab[];
     const int M = P.M, nx = P.nx, ny = P.ny;
     const int i = c % nx, j = c / nx;
-    const double *fr[4] = {recx + (long)(j * (nx + 1) + i) * NT * REC, recx + (long)(j * (nx + 1) + i + 1) * NT * REC,
-                           recy + (long)(j * nx + i) * NT * REC, recy + (long)((j + 1) * nx + i) * NT * REC};
-    const double *cr = crec + (long)c * NT * CREC;
+    const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
+                                      G(recy) + (long)(j * nx + i) * NT * REC,
+                                      G(recy) + (long)((j + 1) * nx + i) * NT * REC};
+    const gptr<const double> cr = G(crec) + (long)c * NT * CREC;
     build_tables<NT>(P, fr, cr, tab);
     __syncthreads();
     const double *ctab = tab + 12 * NT * M;
-    const long sx = (long)NT * P.nvp, sy = (long)nx * NT * P.nvp;
+    const long sx = (long)NT * P.ls, sy = (long)nx * NT * P.ls;
     const double dG = dtc[c];
-    const double rdx = P.rdx[i], rdy = P.rdy[j];
-    const double dxe = P.xf[i + 1] - P.xc[i], dxw = P.xf[i] - P.xc[i];
-    const double dyn = P.yf[j + 1] - P.yc[j], dys = P.yf[j] - P.yc[j];
+    const double rdx = G(P.rdx)[i], rdy = G(P.rdy)[j];
+    const double dxe = G(P.xf)[i + 1] - G(P.xc)[i], dxw = G(P.xf)[i] - G(P.xc)[i];
+    const double dyn = G(P.yf)[j + 1] - G(P.yc)[j], dys = G(P.yf)[j] - G(P.yc)[j];
+    // stencil offsets clamped to the cell itself at the walls: every load is
+    // unconditional (the one-sided slopes never read a clamped value)
+    const int mx = wall_mode(i, nx), my = wall_mode(j, ny);
+    const long oW = mx == 1 ? 0 : -sx, oE = mx == 2 ? 0 : sx, oS = my == 1 ? 0 : -sy, oN = my == 2 ? 0 : sy;
+    const double rxm = G(P.rcx)[i], rxp = G(P.rcx)[i + 1], rym = G(P.rcy)[j], ryp = G(P.rcy)[j + 1];
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
         if (r >= P.Q) continue;
-        const double u = P.vu[ap], v = P.vv[ap];
-        const int iu = P.viu[ap], iv = P.viv[ap];
+        const double u = G(P.vu)[ap], v = G(P.vv)[ap];
+        const int iu = G(P.viu)[ap], iv = G(P.viv)[ap];
         const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0 ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0 ? 1 : 0);
@@ -884,22 +909,36 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
         const int iU = su ? i - 1 : i + 1, jV = sv ? j - 1 : j + 1;
         const long oU = su ? -sx : sx, oV = sv ? -sy : sy;
         const double dxo = su ? dxe : dxw, dyo = sv ? dyn : dys;
-        const double dxi = inx_wall ? 0.0 : (su ? P.xf[i] - P.xc[iU] : P.xf[i + 1] - P.xc[iU]);
-        const double dyi = iny_wall ? 0.0 : (sv ? P.yf[j] - P.yc[jV] : P.yf[j + 1] - P.yc[jV]);
+        const double dxi = inx_wall ? 0.0 : (su ? G(P.xf)[i] - G(P.xc)[iU] : G(P.xf)[i + 1] - G(P.xc)[iU]);
+        const double dyi = iny_wall ? 0.0 : (sv ? G(P.yf)[j] - G(P.yc)[jV] : G(P.yf)[j + 1] - G(P.yc)[jV]);
+        // upwind neighbours U (x) and V (y), the cell itself where the wall is upwind
+        const int iUc = inx_wall ? i : iU, jVc = iny_wall ? j : jV;
+        const long oUc = inx_wall ? 0 : oU, oVc = iny_wall ? 0 : oV;
+        const int mUx = wall_mode(iUc, nx), mVy = wall_mode(jVc, ny);
+        const long oUF = (su ? mUx == 1 : mUx == 2) ? 0 : oU;  // far neighbour of U, relative to U
+        const long oVF = (sv ? mVy == 1 : mVy == 2) ? 0 : oV;  // far neighbour of V, relative to V
+        const double rUm = G(P.rcx)[iUc], rUp = G(P.rcx)[iUc + 1], rVm = G(P.rcy)[jVc], rVp = G(P.rcy)[jVc + 1];
         double hk[NT], bk[NT], dh[NT], db[NT];
-        const long e0 = (long)c * NT * P.nvp + ap;
+        const long e0 = (long)c * NT * P.ls + ap;
 #pragma unroll 1
         for (int n = 0; n < NT; n++) {
-            const TS *hp = h + e0 + (long)n * P.nvp, *bp = b + e0 + (long)n * P.nvp;
+            const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
             const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
-            const double hW = i > 0 ? ldv<TS>(hp, -sx, rh) : 0.0, bW = i > 0 ? ldv<TS>(bp, -sx, rb) : 0.0;
-            const double hE = i < nx - 1 ? ldv<TS>(hp, sx, rh) : 0.0, bE = i < nx - 1 ? ldv<TS>(bp, sx, rb) : 0.0;
-            const double hS = j > 0 ? ldv<TS>(hp, -sy, rh) : 0.0, bS = j > 0 ? ldv<TS>(bp, -sy, rb) : 0.0;
-            const double hN = j < ny - 1 ? ldv<TS>(hp, sy, rh) : 0.0, bN = j < ny - 1 ? ldv<TS>(bp, sy, rb) : 0.0;
+            const double hW = ldv<TS>(hp, oW, rh), bW = ldv<TS>(bp, oW, rb);
+            const double hE = ldv<TS>(hp, oE, rh), bE = ldv<TS>(bp, oE, rb);
+            const double hS = ldv<TS>(hp, oS, rh), bS = ldv<TS>(bp, oS, rb);
+            const double hN = ldv<TS>(hp, oN, rh), bN = ldv<TS>(bp, oN, rb);
+            const TS *hq = hp + oUc, *bq = bp + oUc, *hr = hp + oVc, *br = bp + oVc;
+            const double hUF = ldv<TS>(hq, oUF, rh), bUF = ldv<TS>(bq, oUF, rb);
+            const double hUs = ldv<TS>(hq, oS, rh), bUs = ldv<TS>(bq, oS, rb);
+            const double hUn = ldv<TS>(hq, oN, rh), bUn = ldv<TS>(bq, oN, rb);
+            const double hVF = ldv<TS>(hr, oVF, rh), bVF = ldv<TS>(br, oVF, rb);
+            const double hVw = ldv<TS>(hr, oW, rh), bVw = ldv<TS>(br, oW, rb);
+            const double hVe = ldv<TS>(hr, oE, rh), bVe = ldv<TS>(br, oE, rb);
             hk[n] = hc;
             bk[n] = bc;
-            const double sxh = slope3(hW, hc, hE, i, nx, P.rcx), sxb = slope3(bW, bc, bE, i, nx, P.rcx);
-            const double syh = slope3(hS, hc, hN, j, ny, P.rcy), syb = slope3(bS, bc, bN, j, ny, P.rcy);
+            const double sxh = slope_c(hW, hc, hE, mx, rxm, rxp), sxb = slope_c(bW, bc, bE, mx, rxm, rxp);
+            const double syh = slope_c(hS, hc, hN, my, rym, ryp), syb = slope_c(bS, bc, bN, my, rym, ryp);
             const double sh = u * sxh + v * syh, sb = u * sxb + v * syb;
             const double *tbx = tab + (fxo * NT + n) * 3 * M;
             const double *tbxi = tab + (fxi * NT + n) * 3 * M;
@@ -917,14 +956,9 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
                 face_flux(rxi, exi, u, v, 0.0, 0.0, 0.0, 0.0, Hxi, Bxi);
             } else {
                 const double hU = su ? hW : hE, bU = su ? bW : bE;
-                const TS *hq = hp + oU, *bq = bp + oU;
-                const bool far = su ? (iU > 0) : (iU < nx - 1);
-                const double hF = far ? ldv<TS>(hq, oU, rh) : 0.0, bF = far ? ldv<TS>(bq, oU, rb) : 0.0;
-                const double hUs = j > 0 ? ldv<TS>(hq, -sy, rh) : 0.0, bUs = j > 0 ? ldv<TS>(bq, -sy, rb) : 0.0;
-                const double hUn = j < ny - 1 ? ldv<TS>(hq, sy, rh) : 0.0, bUn = j < ny - 1 ? ldv<TS>(bq, sy, rb) : 0.0;
-                const double sxhU = su ? slope3(hF, hU, hc, iU, nx, P.rcx) : slope3(hc, hU, hF, iU, nx, P.rcx);
-                const double sxbU = su ? slope3(bF, bU, bc, iU, nx, P.rcx) : slope3(bc, bU, bF, iU, nx, P.rcx);
-                const double syhU = slope3(hUs, hU, hUn, j, ny, P.rcy), sybU = slope3(bUs, bU, bUn, j, ny, P.rcy);
+                const double sxhU = su ? slope_c(hUF, hU, hc, mUx, rUm, rUp) : slope_c(hc, hU, hUF, mUx, rUm, rUp);
+                const double sxbU = su ? slope_c(bUF, bU, bc, mUx, rUm, rUp) : slope_c(bc, bU, bUF, mUx, rUm, rUp);
+                const double syhU = slope_c(hUs, hU, hUn, my, rym, ryp), sybU = slope_c(bUs, bU, bUn, my, rym, ryp);
                 face_flux(rxi, exi, u, v, hU + sxhU * dxi, bU + sxbU * dxi, u * sxhU + v * syhU, u * sxbU + v * sybU,
                           Hxi, Bxi);
             }
@@ -933,14 +967,9 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
                 face_flux(ryi, eyi, v, u, 0.0, 0.0, 0.0, 0.0, Hyi, Byi);
             } else {
                 const double hV = sv ? hS : hN, bV = sv ? bS : bN;
-                const TS *hq = hp + oV, *bq = bp + oV;
-                const bool far = sv ? (jV > 0) : (jV < ny - 1);
-                const double hF = far ? ldv<TS>(hq, oV, rh) : 0.0, bF = far ? ldv<TS>(bq, oV, rb) : 0.0;
-                const double hVw = i > 0 ? ldv<TS>(hq, -sx, rh) : 0.0, bVw = i > 0 ? ldv<TS>(bq, -sx, rb) : 0.0;
-                const double hVe = i < nx - 1 ? ldv<TS>(hq, sx, rh) : 0.0, bVe = i < nx - 1 ? ldv<TS>(bq, sx, rb) : 0.0;
-                const double syhV = sv ? slope3(hF, hV, hc, jV, ny, P.rcy) : slope3(hc, hV, hF, jV, ny, P.rcy);
-                const double sybV = sv ? slope3(bF, bV, bc, jV, ny, P.rcy) : slope3(bc, bV, bF, jV, ny, P.rcy);
-                const double sxhV = slope3(hVw, hV, hVe, i, nx, P.rcx), sxbV = slope3(bVw, bV, bVe, i, nx, P.rcx);
+                const double syhV = sv ? slope_c(hVF, hV, hc, mVy, rVm, rVp) : slope_c(hc, hV, hVF, mVy, rVm, rVp);
+                const double sybV = sv ? slope_c(bVF, bV, bc, mVy, rVm, rVp) : slope_c(bc, bV, bVF, mVy, rVm, rVp);
+                const double sxhV = slope_c(hVw, hV, hVe, mx, rxm, rxp), sxbV = slope_c(bVw, bV, bVe, mx, rxm, rxp);
                 face_flux(ryi, eyi, v, u, hV + syhV * dyi, bV + sybV * dyi, u * sxhV + v * syhV, u * sxbV + v * sybV,
                           Hyi, Byi);
             }
@@ -970,11 +999,11 @@ template <typename TS>
 __global__ void k_init(Params P, TS *h, TS *b, double *W)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long nel = (long)P.nc * P.NT * P.nvp;
+    const long nel = (long)P.nc * P.NT * P.ls;
     if (t < nel) {
-        const int ap = t % P.nvp;
-        const bool valid = (ap % P.Qp) < P.Q;
-        const double u = P.vu[ap], v = P.vv[ap];
+        const int ap = t % P.ls;
+        const bool valid = ap < P.nvp && (ap % P.Qp) < P.Q;
+        const double u = valid ? P.vu[ap] : 0.0, v = valid ? P.vv[ap] : 0.0;
         const double H = valid ? exp(-(u * u + v * v)) / HB_PI : 0.0;
         if constexpr (sizeof(TS) == 4) {
             h[t] = 0.0f;  // rest state: deviation from H_ref is zero
@@ -1025,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_harm_vars(Params P, const TS *__restric
         prim4(P.K, W + ((long)c * P.NT + n) * 4, p);
         double s0 = 0, s1 = 0, s2 = 0;
         for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
-            const long e = ((long)c * P.NT + n) * P.nvp + ap;
+            const long e = ((long)c * P.NT + n) * P.ls + ap;
             const double w = P.vw[ap], cu = P.vu[ap] - p[1], cv = P.vv[ap] - p[2];
             const double rh = href_of<TS>(P, ap);
             const double hh = ldv<TS>(h, e, rh), en = (cu * cu + cv * cv) * hh + ldv<TS>(b, e, 0.5 * P.K * rh);

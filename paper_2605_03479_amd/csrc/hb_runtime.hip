@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -228,6 +229,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.Q = P.Mh * P.Mh;
     P.Qp = (P.Q + 63) / 64 * 64;
     P.nvp = 4 * P.Qp;
+    P.ls = P.nvp;
     P.NH = NH;
     P.NT = 2 * NH + 1;
     P.K = nm.K_int;
@@ -314,7 +316,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
             if (r < P.Q) H->perm[(size_t)iv * M + iu] = ap;
         }
 
-    const size_t nel = (size_t)P.nc * NT * nvp;
+    const size_t nel = (size_t)P.nc * NT * P.ls;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     H->cells_blocks = (P.nc * NT + 127) / 128;
     H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
@@ -523,12 +525,12 @@ int hb_ugks_state_out(hb_handle H, double *W, double *hh, double *bb, size_t cap
     double *dst[2] = {hh, bb};
     for (int s = 0; s < 2; s++) {
         if (!dst[s]) continue;
-        tmp.resize(ncn * P.nvp * eb);
+        tmp.resize(ncn * P.ls * eb);
         HIPOK(hipMemcpy(tmp.data(), src[s], tmp.size(), hipMemcpyDeviceToHost));
         const double fac = s == 0 ? 1.0 : 0.5 * P.K;
         for (size_t e = 0; e < ncn; e++)
             for (size_t a = 0; a < nv; a++) {
-                const size_t k = e * P.nvp + H->perm[a];
+                const size_t k = e * P.ls + H->perm[a];
                 dst[s][e * nv + a] = mixed ? (double)((const float *)tmp.data())[k] + fac * H->vref_host[H->perm[a]]
                                            : ((const double *)tmp.data())[k];
             }
@@ -552,11 +554,11 @@ int hb_ugks_state_in(hb_handle H, const double *W, const double *hh, const doubl
     const double *src[2] = {hh, bb};
     for (int s = 0; s < 2; s++) {
         if (!src[s]) continue;
-        tmp.assign(ncn * P.nvp * eb, 0);
+        tmp.assign(ncn * P.ls * eb, 0);
         const double fac = s == 0 ? 1.0 : 0.5 * P.K;
         for (size_t e = 0; e < ncn; e++)
             for (size_t a = 0; a < nv; a++) {
-                const size_t k = e * P.nvp + H->perm[a];
+                const size_t k = e * P.ls + H->perm[a];
                 if (mixed)
                     ((float *)tmp.data())[k] = (float)(src[s][e * nv + a] - fac * H->vref_host[H->perm[a]]);
                 else
