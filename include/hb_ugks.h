@@ -225,6 +225,46 @@ int hb_batch_use_graph(hb_batch_handle b, int on);
 int hb_batch_pool_info(hb_batch_handle b, size_t *capacity, size_t *in_use, size_t *largest_free);
 void hb_batch_destroy(hb_batch_handle b);
 
+/* ------------------------------------------------------------------ serving
+ * A frequency-response solve requested at arrival_s (seconds after the run
+ * starts): the case, as for hb_batch_add, and where its converged harmonics
+ * go (var_mask, re, im, capacity as for hb_ugks_harmonics_out; re/im NULL:
+ * none). */
+typedef struct {
+    hb_geometry geo;
+    double Kn, St;
+    int n_harmonics;
+    hb_wall walls[4];
+    hb_vgrid vg;
+    int has_numerics;   /* 0: default numerics */
+    hb_numerics num;
+    int precision;      /* hb_precision */
+    double arrival_s;
+    unsigned var_mask;
+    double *re, *im;
+    size_t capacity;
+} hb_request;
+
+typedef struct {
+    int status;          /* HB_OK converged; HB_EDIVERGED; HB_ENOMEM larger than the pool; HB_ESTATE max_steps hit */
+    long steps;          /* pseudo steps taken by the case */
+    double residual[4];  /* Eq. 43 at the last check */
+    double t_admit, t_done;  /* seconds after the run starts (-1: never) */
+    size_t bytes;        /* device footprint while resident */
+} hb_result;
+
+/* Serve n requests (in arrival order) on an empty batch: admit each arrived
+ * request as soon as its footprint fits the pool (later requests may pass one
+ * that does not fit yet), advance the batch check_every steps at a time, and
+ * retire every case whose density residual is <= tol (its harmonics are
+ * copied out and its memory freed at once) or that reaches max_steps.
+ * Admission and checks happen only between chunks, so a request's steps and
+ * result are the same alone and in any mix.  Blocks until every request is
+ * retired; *wall_s (may be NULL) receives the run's duration.
+ * Errors: HB_EINVAL, HB_ESTATE (the batch holds cases), HB_EDEVICE. */
+int hb_serve_run(hb_batch_handle b, const hb_request *req, int n, double tol, int check_every, long max_steps,
+                 hb_result *out, double *wall_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,13 +46,26 @@ class hb_numerics(ctypes.Structure):
                 ("dt_mode", ctypes.c_int), ("dt_fixed", ctypes.c_double)]
 
 
+class hb_request(ctypes.Structure):
+    _fields_ = [("geo", hb_geometry), ("Kn", ctypes.c_double), ("St", ctypes.c_double), ("n_harmonics", ctypes.c_int),
+                ("walls", hb_wall * 4), ("vg", hb_vgrid), ("has_numerics", ctypes.c_int), ("num", hb_numerics),
+                ("precision", ctypes.c_int), ("arrival_s", ctypes.c_double), ("var_mask", ctypes.c_uint),
+                ("re", _D), ("im", _D), ("capacity", ctypes.c_size_t)]
+
+
+class hb_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_long), ("residual", ctypes.c_double * 4),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
 EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
            "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
            "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
            "hb_ugks_destroy", "hb_ugks_strerror",
            "hb_batch_create", "hb_batch_case_bytes", "hb_batch_add", "hb_batch_remove", "hb_batch_set_active",
            "hb_batch_step", "hb_batch_residuals", "hb_batch_case", "hb_batch_tune", "hb_batch_shapes",
-           "hb_batch_use_graph", "hb_batch_set_cache_bytes", "hb_batch_pool_info", "hb_batch_destroy")
+           "hb_batch_use_graph", "hb_batch_set_cache_bytes", "hb_batch_pool_info", "hb_batch_destroy",
+           "hb_serve_run")
 
 _LIB = None
 
@@ -103,6 +116,9 @@ def load_library(path=None):
     L.hb_batch_pool_info.argtypes = [vp, szp, szp, szp]
     L.hb_batch_destroy.argtypes = [vp]
     L.hb_batch_destroy.restype = None
+    L.hb_serve_run.argtypes = [vp, ctypes.POINTER(hb_request), ip, dp, ip, ctypes.c_long, ctypes.POINTER(hb_result),
+                               ctypes.POINTER(dp)]
+    L.hb_serve_run.restype = ctypes.c_int
     for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_residual",
                  "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
                  "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
@@ -442,3 +458,40 @@ class Batch:
 
     def pool_info(self):
         return hb_batch_pool_info(self.b)
+
+
+# ------------------------------------------------------------- serving
+def serve(batch, cases, arrivals, precision=HB_MIXED, tol=1e-8, check_every=100, max_steps=200000,
+          var_mask=0x7F):
+    """Run the serving loop (hb_serve_run) on an empty Batch.  Returns
+    (results: list of dicts, harmonics: list of (re, im) or None, wall seconds)."""
+    n = len(cases)
+    reqs = (hb_request * n)()
+    keep = []
+    harm = []
+    for k, (c, t) in enumerate(zip(cases, arrivals)):
+        g, walls, vg, nm, kk = _case_args(c)
+        keep.append(kk)
+        nsel = bin(var_mask & 0x7F).count("1")
+        re = np.zeros((nsel, c.NH + 1, c.nx * c.ny))
+        im = np.zeros_like(re)
+        harm.append((re, im))
+        r = reqs[k]
+        r.geo = g
+        r.Kn, r.St, r.n_harmonics = c.Kn, c.St, c.NH
+        for w in range(4):
+            r.walls[w] = walls[w]
+        r.vg = vg
+        r.has_numerics = 1
+        r.num = nm
+        r.precision = precision
+        r.arrival_s = float(t)
+        r.var_mask = var_mask
+        r.re, r.im, r.capacity = _dp(re), _dp(im), re.size
+    out = (hb_result * n)()
+    wall = ctypes.c_double()
+    _check(load_library().hb_serve_run(batch.b, reqs, n, float(tol), int(check_every), int(max_steps), out,
+                                       ctypes.byref(wall)), "hb_serve_run")
+    res = [dict(status=o.status, steps=o.steps, residual=list(o.residual), t_admit=o.t_admit, t_done=o.t_done,
+                arrival=float(t), bytes=o.bytes) for o, t in zip(out, arrivals)]
+    return res, [h if r["status"] == HB_OK else None for h, r in zip(harm, res)], wall.value

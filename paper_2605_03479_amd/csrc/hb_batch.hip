@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -747,3 +748,107 @@ int hb_batch_use_graph(hb_batch_handle B, int on)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ serving
+// Requests arrive at given times (seconds from the start of the run).  The
+// loop admits every arrived request whose device footprint fits the pool now
+// (FIFO, later requests may pass one that does not fit yet), advances the
+// batch check_every steps at a time, and retires each case whose density
+// residual (Eq. 43) is at or below tol: its harmonics go to the request's
+// buffers and its memory returns to the pool at once.  Admission and checks
+// happen only between chunks of check_every steps, so a request's step count
+// and result do not depend on what else is in the mix.
+namespace {
+double wall_now()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, double tol, int check_every,
+                            long max_steps, hb_result *out, double *wall_s)
+{
+    if (!B || (n > 0 && (!req || !out)) || n < 0 || check_every <= 0 || max_steps <= 0 || !(tol > 0.0))
+        return HB_EINVAL;
+    for (int k = 0; k < B->max_cases; k++)
+        if (B->cases[k]) return HB_ESTATE;  // the run owns the batch
+    for (int k = 0; k < n; k++) {
+        out[k] = hb_result{};
+        out[k].status = HB_ESTATE;
+        out[k].t_admit = out[k].t_done = -1.0;
+    }
+    std::vector<int> slot_req(B->max_cases, -1);
+    std::vector<size_t> need(n, 0);
+    for (int k = 0; k < n; k++) {
+        int rc = hb_batch_case_bytes(B, req[k].precision, &req[k].geo, req[k].n_harmonics, &req[k].vg, &need[k]);
+        if (rc != HB_OK) return rc;
+    }
+    const double t0 = wall_now();
+    int done = 0, next = 0, active = 0;
+    std::vector<char> pending(n, 0);
+    std::vector<double> res(4 * (size_t)B->max_cases);
+    std::vector<long> steps(B->max_cases);
+    std::vector<int> div(B->max_cases), ids(B->max_cases);
+    while (done < n) {
+        const double now = wall_now() - t0;
+        while (next < n && req[next].arrival_s <= now) pending[next++] = 1;
+        // admission in arrival order; a request that can never fit is refused
+        for (int k = 0; k < next; k++) {
+            if (!pending[k]) continue;
+            if (need[k] > B->pool.size) {
+                pending[k] = 0;
+                out[k].status = HB_ENOMEM;
+                out[k].t_done = now;
+                done++;
+                continue;
+            }
+            if (need[k] > B->pool.largest_free()) continue;
+            int cid = -1;
+            const hb_request &r = req[k];
+            int rc = hb_batch_add(B, r.precision, &r.geo, r.Kn, r.St, r.n_harmonics, r.walls, &r.vg,
+                                  r.has_numerics ? &r.num : nullptr, &cid);
+            if (rc == HB_ENOMEM || rc == HB_ECAPACITY) continue;  // not now
+            if (rc != HB_OK) return rc;
+            pending[k] = 0;
+            slot_req[cid] = k;
+            out[k].t_admit = wall_now() - t0;
+            out[k].bytes = need[k];
+            active++;
+        }
+        if (active == 0) {
+            if (next < n) {  // idle until the next arrival
+                const double wait = req[next].arrival_s - (wall_now() - t0);
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            }
+            continue;
+        }
+        int rc = hb_batch_step(B, check_every);
+        if (rc != HB_OK) return rc;
+        const int na = hb_batch_residuals(B, res.data(), steps.data(), div.data(), ids.data(), B->max_cases);
+        if (na < 0) return na;
+        for (int a = 0; a < na; a++) {
+            const int cid = ids[a], k = slot_req[cid];
+            if (k < 0) continue;
+            const bool conv = res[4 * a] <= tol, bad = div[a] != 0, late = steps[a] >= max_steps;
+            if (!conv && !bad && !late) continue;
+            hb_result &o = out[k];
+            o.steps = steps[a];
+            for (int q = 0; q < 4; q++) o.residual[q] = res[4 * a + q];
+            o.status = bad ? HB_EDIVERGED : (conv ? HB_OK : HB_ESTATE);
+            if (conv && !bad && req[k].re && req[k].im) {
+                hb_handle H = nullptr;
+                if ((rc = hb_batch_case(B, cid, &H)) != HB_OK) return rc;
+                rc = hb_ugks_harmonics_out(H, req[k].var_mask, req[k].re, req[k].im, req[k].capacity);
+                if (rc != HB_OK) o.status = rc;
+            }
+            if ((rc = hb_batch_remove(B, cid)) != HB_OK) return rc;
+            slot_req[cid] = -1;
+            o.t_done = wall_now() - t0;
+            active--;
+            done++;
+        }
+    }
+    if (wall_s) *wall_s = wall_now() - t0;
+    return HB_OK;
+}

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "hb_ugks.h")).read()
-    return sorted(set(re.findall(r"\b(hb_(?:ugks|batch)_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(hb_(?:ugks|batch|serve)_\w+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
