@@ -70,6 +70,89 @@ def traffic_bytes(workload, precision, kernel):
     return MEASURED_TRAFFIC["bytes"].get(f"{workload}/{precision}/{kernel}")
 
 
+def batched_sweep(hb, hbcases, steps=5):
+    """The 64-case seeded sweep: one batch step of the tuned mixed batch
+    against the plain FP64 solver stepping the same cases one at a time."""
+    cases = hbcases.batch_sweep()
+    tot = sum(c.updates for c in cases)
+    B = hb.Batch(max_cases=len(cases))
+    for c in cases:
+        B.add(c, hb.HB_MIXED)
+    B.tune(2)
+    B.step(1)
+    B.residuals()
+    t0 = time.perf_counter()
+    B.step(steps)
+    r = B.residuals()
+    t_batch = (time.perf_counter() - t0) / steps
+    diverged = sum(1 for v in r.values() if v[2])
+    B.close()
+    t_plain = 0.0
+    for c in cases:
+        s = hb.Solver(c)
+        s.step(1)
+        s.residual()
+        t0 = time.perf_counter()
+        s.step(3)
+        s.residual()
+        t_plain += (time.perf_counter() - t0) / 3
+        s.close()
+    log(f"batched sweep: mixed batch {t_batch * 1e3:.1f} ms/step, plain fp64 one at a time {t_plain * 1e3:.1f} ms")
+    return {"workload": "batch_sweep_64_seed260503479", "updates_per_step": tot,
+            "batched_mixed_ms_per_step": t_batch * 1e3, "batched_mixed_updates_per_s": tot / t_batch,
+            "plain_fp64_ms_per_step": t_plain * 1e3, "plain_fp64_updates_per_s": tot / t_plain,
+            "speedup_batched_vs_plain": t_plain / t_batch, "diverged": diverged}
+
+
+def serving(hb, hbcases, check_every=100, max_steps=20000, tol=1e-8):
+    """Serving loop on the seeded request set: converged cases/h of the batched
+    mixed form (all requests present at once) against the plain FP64 solver
+    running them one at a time to the same residual, then p50/p99
+    time-to-converged under Poisson arrivals at 0.8 of the batched capacity."""
+    import numpy as np
+    reqs = hbcases.serving_requests()
+    n = len(reqs)
+    B = hb.Batch(max_cases=n)
+    res, _, wall = hb.serve(B, reqs, [0.0] * n, precision=hb.HB_MIXED, tol=tol, check_every=check_every,
+                            max_steps=max_steps)
+    B.close()
+    conv = sum(1 for r in res if r["status"] == hb.HB_OK)
+    cap = conv / wall
+    t0 = time.perf_counter()
+    conv_plain = 0
+    for c in reqs:
+        s = hb.Solver(c)
+        k = 0
+        while k < max_steps:
+            s.step(check_every)
+            k += check_every
+            try:
+                if s.residual()[0] <= tol:
+                    conv_plain += 1
+                    break
+            except hb.HBError:
+                break
+        s.close()
+    wall_plain = time.perf_counter() - t0
+    rate = 0.8 * cap
+    arr = hbcases.poisson_arrivals(n, rate)
+    B = hb.Batch(max_cases=n)
+    res2, _, wall2 = hb.serve(B, reqs, arr, precision=hb.HB_MIXED, tol=tol, check_every=check_every,
+                              max_steps=max_steps)
+    B.close()
+    lat = np.array([r["t_done"] - r["arrival"] for r in res2 if r["status"] == hb.HB_OK])
+    out = {"workload": f"serving_{n}_requests_seed260503480", "requests": n, "converged_batched": conv,
+           "converged_plain_fp64": conv_plain,
+           "batched_mixed_cases_per_h": 3600.0 * conv / wall, "plain_fp64_cases_per_h": 3600.0 * conv_plain / wall_plain,
+           "poisson_rate_per_s": rate, "served_under_arrivals": int(len(lat)),
+           "p50_time_to_converged_s": float(np.percentile(lat, 50)) if len(lat) else None,
+           "p99_time_to_converged_s": float(np.percentile(lat, 99)) if len(lat) else None,
+           "arrival_run_wall_s": wall2}
+    log(f"serving: batched {out['batched_mixed_cases_per_h']:.0f} cases/h vs plain {out['plain_fp64_cases_per_h']:.0f}; "
+        f"p50 {out['p50_time_to_converged_s']} s p99 {out['p99_time_to_converged_s']} s")
+    return out
+
+
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -202,6 +285,11 @@ def main():
                           "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
 
+    batched = serving_res = None
+    if not args.no_extra:
+        batched = batched_sweep(hb, hbcases)
+        serving_res = serving(hb, hbcases)
+
     out = {
         "metric": METRIC, "value": ups, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -214,6 +302,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "other_workloads": extra,
+        "batched": batched,
+        "serving": serving_res,
     }
     print(json.dumps(out), flush=True)
 

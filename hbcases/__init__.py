@@ -133,6 +133,39 @@ def batch_sweep(n=64, seed=260503479):
     return out
 
 
+def serving_requests(n=24, seed=260503480, outlier_p=1.0 / 16.0):
+    """Seeded frequency-response requests for the serving loop, drawn like the
+    batched sweep on a scale whose cases converge within seconds: grid side
+    U{12..32}, velocity side U{12..24} (even), NH U{1..2}, Kn log-uniform
+    [0.3, 10], St log-uniform [0.1, 0.5], half shear (lid 0.01, [-4,4]) and
+    half thermal (bottom wall, dT U(0.1, 0.2), [-5,5]); with probability
+    outlier_p an outlier of 48 x 48 cells, 32 x 32 velocities, NH = 3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        if rng.uniform() < outlier_p:
+            out.append(Case(48, 48, 32, 4.0, 1.0, 0.5, 3, lid_walls(0.01), name=f"req{k}_outlier"))
+            continue
+        N = int(rng.integers(12, 33))
+        M = int(rng.integers(12, 25))
+        M += M % 2
+        NH = int(rng.integers(1, 3))
+        Kn = float(10.0 ** rng.uniform(np.log10(0.3), 1.0))
+        St = float(10.0 ** rng.uniform(-1.0, np.log10(0.5)))
+        if k % 2 == 0:
+            out.append(Case(N, N, M, 4.0, Kn, St, NH, lid_walls(0.01), name=f"req{k}_shear"))
+        else:
+            dT = float(rng.uniform(0.1, 0.2))
+            out.append(Case(N, N, M, 5.0, Kn, St, NH, thermal_walls(dT, 0, "sin"), name=f"req{k}_thermal"))
+    return out
+
+
+def poisson_arrivals(n, rate, seed=260503481):
+    """Arrival times (s) of a Poisson process of the given rate (1/s)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
 # ----------------------------------------------------------------- seeded noise
 def noise(shape, seed, scale=1.0):
     """Seeded standard-normal numbers times `scale` (PCG64)."""
