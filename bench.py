@@ -8,6 +8,7 @@ HBM.  value = cell x velocity x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
                   [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
+                  [--only batch|serving]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -29,14 +30,14 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "a0c0c2492bdf815d",
+    "sources_sha256_16": "f71dadb2de6000cf",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 608406217,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 1059849812,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 166544138,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 2072733056,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 3855919241,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 857305532,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 608286685,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 1062290028,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 166358268,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 2079932765,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 3862149058,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 811674084,
     },
 }
 
@@ -187,6 +188,8 @@ def main():
     ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
                     help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--only", choices=("batch", "serving"), default=None,
+                    help="run only the batched sweep or the serving measurement (prints its JSON)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -222,6 +225,11 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
+
+    if args.only:
+        res = batched_sweep(hb, hbcases) if args.only == "batch" else serving(hb, hbcases)
+        print(json.dumps(res), flush=True)
+        return
 
     prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
     case = hbcases.shear_cavity(args.kn, args.st) if args.workload == "shear" else \
