@@ -111,6 +111,27 @@ int hb_ugks_set_case(hb_handle h, const hb_geometry *geo, double Kn, double St, 
  * Errors: HB_ESTATE (no case), HB_EINVAL (nsteps < 0), HB_EDEVICE. */
 int hb_ugks_pseudo_step(hb_handle h, int nsteps);
 
+/* Explicit time-domain UGKS, the comparison solver of Sec. 3.1.4: the same
+ * flux and update as a pseudo step with one level (n_harmonics = 0, so the
+ * spectral term of Eq. 17 vanishes) and one physical step dt_fixed for every
+ * cell (numerics dt_mode = 1).  Before each step the walls take their
+ * Eqs. (25)-(26) values at the mid-step phase omega (t + dt/2); t starts at 0
+ * in set_case and grows by dt_fixed per step.  Queues and returns without
+ * synchronising.  A later hb_ugks_pseudo_step keeps the last wall state.
+ * Errors: HB_ESTATE (no case, n_harmonics != 0 or dt_mode != 1, or the case
+ * belongs to a batch), HB_EINVAL (nsteps < 0), HB_EDEVICE. */
+int hb_ugks_td_step(hb_handle h, int nsteps);
+
+/* nsteps time-domain steps (one forcing period when nsteps * dt_fixed =
+ * 2 pi / St), then the period residual of Eq. (43), second line: the RMS
+ * over cells of W(t_end) - W(t_start) for (rho, rho U, rho V, rho E), into
+ * out[4].  Synchronises.  Errors: as hb_ugks_td_step (nsteps < 1 is
+ * HB_EINVAL), HB_EDIVERGED (NaN/Inf in any step or in out). */
+int hb_ugks_td_period(hb_handle h, int nsteps, double out[4]);
+
+/* Physical time reached by the time-domain steps of this case. */
+int hb_ugks_time(hb_handle h, double *t);
+
 /* Residual of the last completed step, Eq. (43): RMS over cells of the
  * level-0 change of (rho, rho U, rho V, rho E).  Synchronises the stream.
  * step_index (may be NULL) receives the number of steps taken.

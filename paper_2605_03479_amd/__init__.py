@@ -59,6 +59,7 @@ class hb_result(ctypes.Structure):
 
 
 EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
+           "hb_ugks_td_step", "hb_ugks_td_period", "hb_ugks_time",
            "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
            "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
            "hb_ugks_destroy", "hb_ugks_strerror",
@@ -86,6 +87,9 @@ def load_library(path=None):
     L.hb_ugks_set_case.argtypes = [vp, ctypes.POINTER(hb_geometry), dp, dp, ip, ctypes.POINTER(hb_wall),
                                    ctypes.POINTER(hb_vgrid), ctypes.POINTER(hb_numerics)]
     L.hb_ugks_pseudo_step.argtypes = [vp, ip]
+    L.hb_ugks_td_step.argtypes = [vp, ip]
+    L.hb_ugks_td_period.argtypes = [vp, ip, _D]
+    L.hb_ugks_time.argtypes = [vp, ctypes.POINTER(dp)]
     L.hb_ugks_residual.argtypes = [vp, _D, ctypes.POINTER(ctypes.c_long)]
     L.hb_ugks_harmonics_out.argtypes = [vp, ctypes.c_uint, _D, _D, sz]
     L.hb_ugks_state_out.argtypes = [vp, _D, _D, _D, sz]
@@ -119,7 +123,8 @@ def load_library(path=None):
     L.hb_serve_run.argtypes = [vp, ctypes.POINTER(hb_request), ip, dp, ip, ctypes.c_long, ctypes.POINTER(hb_result),
                                ctypes.POINTER(dp)]
     L.hb_serve_run.restype = ctypes.c_int
-    for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_residual",
+    for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_td_step",
+                 "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_residual",
                  "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
                  "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
                  "hb_batch_add", "hb_batch_remove", "hb_batch_set_active", "hb_batch_step", "hb_batch_residuals",
@@ -183,6 +188,22 @@ def hb_ugks_set_case(h, case):
 
 def hb_ugks_pseudo_step(h, nsteps):
     return _check(load_library().hb_ugks_pseudo_step(h, int(nsteps)), "hb_ugks_pseudo_step")
+
+
+def hb_ugks_td_step(h, nsteps):
+    return _check(load_library().hb_ugks_td_step(h, int(nsteps)), "hb_ugks_td_step")
+
+
+def hb_ugks_td_period(h, nsteps):
+    out = np.zeros(4)
+    _check(load_library().hb_ugks_td_period(h, int(nsteps), _dp(out)), "hb_ugks_td_period")
+    return out
+
+
+def hb_ugks_time(h):
+    t = ctypes.c_double()
+    _check(load_library().hb_ugks_time(h, ctypes.byref(t)), "hb_ugks_time")
+    return t.value
 
 
 def hb_ugks_residual(h):
@@ -272,6 +293,15 @@ class Solver:
 
     def step(self, n=1):
         hb_ugks_pseudo_step(self.h, n)
+
+    def td_step(self, n=1):
+        hb_ugks_td_step(self.h, n)
+
+    def td_period(self, nsteps):
+        return hb_ugks_td_period(self.h, nsteps)
+
+    def time(self):
+        return hb_ugks_time(self.h)
 
     def residual(self):
         rc, r, k = hb_ugks_residual(self.h)

@@ -122,6 +122,11 @@ struct hb_ugks {
     std::vector<double> vref_host;
     double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
     int *flag = nullptr;
+    // time-domain form (one level, global step): wall inputs, physical time,
+    // W at the start of the current period and the period residual
+    hb_wall walls[4]{};
+    double t_phys = 0.0;
+    double *Wp = nullptr, *tdres = nullptr;
     int cur = 0;
     long step = 0;
     int cells_blocks = 0;

@@ -651,6 +651,28 @@ __global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart,
     resid_block(rpart, nblk, nc, ring, slot, flag);
 }
 
+// Period residual of the time-domain solver, Eq. (43) second line: RMS over
+// cells of W(nT) - W((n-1)T) for one level (W[c][4]); one block, fixed-order sums.
+__global__ __launch_bounds__(256) void k_period_diff(const double *__restrict__ Wa, const double *__restrict__ Wb,
+                                                     int nc, double *__restrict__ out)
+{
+    __shared__ double red[4][256];
+    double s[4] = {0, 0, 0, 0};
+    for (int c = threadIdx.x; c < nc; c += 256)
+        for (int k = 0; k < 4; k++) {
+            const double d = Wa[(long)c * 4 + k] - Wb[(long)c * 4 + k];
+            s[k] += d * d;
+        }
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sqrt(red[threadIdx.x][0] / nc);
+}
+
 // ---------------------------------------------------------------- K5: update
 // One block per cell, templated on the number of levels so the per-level
 // state of a velocity lives in registers.  LDS holds the 1-D Maxwellian factor

@@ -253,6 +253,9 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
             const int d = n - m;
             P.E[n * NT + m] = d == 0 ? 0.0 : 0.5 * ((d % 2 == 0) ? 1.0 : -1.0) / std::sin(M_PI * d / NT);  // Eq. (17)
         }
+    for (int w = 0; w < 4; w++) H->walls[w] = walls[w];
+    H->t_phys = 0.0;
+    H->Wp = H->tdres = nullptr;
     for (int w = 0; w < 4; w++)
         for (int n = 0; n < NT; n++) {
             const double th = 2.0 * M_PI * n / NT;  // omega t_n, Eq. (12)
@@ -359,6 +362,10 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->n_bnd = (int)bnd.size();
     H->n_int = P.nc - H->n_bnd;
     ALLOC(H->bnd_cells, bnd.size(), int);
+    if (NT == 1 && P.dt_mode == 1) {
+        ALLOC(H->Wp, (size_t)P.nc * 4, double);
+        ALLOC(H->tdres, 4, double);
+    }
 #undef ALLOC
     H->bnd_host = bnd;
     if (H->count_only) return HB_OK;
@@ -412,50 +419,124 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     return HB_OK;
 }
 
+}  // extern "C"
+
+// Queue one step of Sec. 2.4 on the handle's stream and swap the buffers.
+static int enqueue_step(hb_ugks *H)
+{
+    const hb::Params &P = H->P;
+    const int NT = P.NT;
+    const int nfaces = (P.nx + 1) * P.ny + P.nx * (P.ny + 1);
+    const int c = H->cur, x = 1 - c;
+    const int slot = (int)(H->step % HB_RING);
+    hipEvent_t *ev = nullptr;
+    if (H->timing) {
+        if (H->tused + HB_NKERN + 1 > H->tev.size()) {
+            for (int k = 0; k <= HB_NKERN; k++) {
+                hipEvent_t e;
+                HIPOK(hipEventCreate(&e));
+                H->tev.push_back(e);
+            }
+        }
+        ev = H->tev.data() + H->tused;
+        H->tused += HB_NKERN + 1;
+        HIPOK(hipEventRecord(ev[0], H->stream));
+    }
+    launch_moments(H, P, c);
+    if (ev) HIPOK(hipEventRecord(ev[1], H->stream));
+    hipLaunchKernelGGL(hb::k_faces, dim3((nfaces * NT + 127) / 128), dim3(128), 0, H->stream, P, H->feed, H->W[c],
+                       H->dt[c], H->recx, H->recy);
+    if (ev) HIPOK(hipEventRecord(ev[2], H->stream));
+    hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
+                       H->W[c], H->dt[c], H->W[x], H->crec, H->rpart);
+    if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
+    hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
+    if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
+    hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring, slot,
+                       H->flag);
+    if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
+    launch_update(H, P, c, x, ev ? ev[6] : nullptr);
+    if (ev) HIPOK(hipEventRecord(ev[7], H->stream));
+    HIPOK(hipGetLastError());
+    H->cur = x;
+    H->step++;
+    return HB_OK;
+}
+
+extern "C" {
+
 int hb_ugks_pseudo_step(hb_handle H, int nsteps)
 {
     if (!H) return HB_EINVAL;
     if (!H->has_case || H->batch_owned) return HB_ESTATE;
     if (nsteps < 0) return HB_EINVAL;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
-    const hb::Params &P = H->P;
-    const int NT = P.NT;
-    const int nfaces = (P.nx + 1) * P.ny + P.nx * (P.ny + 1);
     for (int s = 0; s < nsteps; s++) {
-        const int c = H->cur, x = 1 - c;
-        const int slot = (int)(H->step % HB_RING);
-        hipEvent_t *ev = nullptr;
-        if (H->timing) {
-            if (H->tused + HB_NKERN + 1 > H->tev.size()) {
-                for (int k = 0; k <= HB_NKERN; k++) {
-                    hipEvent_t e;
-                    HIPOK(hipEventCreate(&e));
-                    H->tev.push_back(e);
-                }
-            }
-            ev = H->tev.data() + H->tused;
-            H->tused += HB_NKERN + 1;
-            HIPOK(hipEventRecord(ev[0], H->stream));
-        }
-        launch_moments(H, P, c);
-        if (ev) HIPOK(hipEventRecord(ev[1], H->stream));
-        hipLaunchKernelGGL(hb::k_faces, dim3((nfaces * NT + 127) / 128), dim3(128), 0, H->stream, P, H->feed, H->W[c],
-                           H->dt[c], H->recx, H->recy);
-        if (ev) HIPOK(hipEventRecord(ev[2], H->stream));
-        hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
-                           H->W[c], H->dt[c], H->W[x], H->crec, H->rpart);
-        if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
-        hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
-        if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
-        hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring,
-                           slot, H->flag);
-        if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
-        launch_update(H, P, c, x, ev ? ev[6] : nullptr);
-        if (ev) HIPOK(hipEventRecord(ev[7], H->stream));
-        HIPOK(hipGetLastError());
-        H->cur = x;
-        H->step++;
+        const int rc = enqueue_step(H);
+        if (rc != HB_OK) return rc;
     }
+    return HB_OK;
+}
+
+// Explicit time-domain UGKS: the wall state of Eqs. (25)-(26) is taken at the
+// physical mid-step time, the spectral term vanishes with one level, and every
+// cell advances by the same physical step dt_fixed.
+static int td_steps(hb_ugks *H, int nsteps)
+{
+    hb::Params &P = H->P;
+    const double dt = P.dt_fixed;
+    for (int s = 0; s < nsteps; s++) {
+        const double th = P.omega * (H->t_phys + 0.5 * dt);
+        const double c = std::cos(th), sn = std::sin(th);
+        for (int w = 0; w < 4; w++) {
+            const hb_wall &wl = H->walls[w];
+            P.wall_ut[w][0] = wl.ut_mean + wl.ut_hat_re * c - wl.ut_hat_im * sn;
+            P.wall_T[w][0] = wl.T_mean + wl.T_hat_re * c - wl.T_hat_im * sn;
+        }
+        const int rc = enqueue_step(H);
+        if (rc != HB_OK) return rc;
+        H->t_phys += dt;
+    }
+    return HB_OK;
+}
+
+static bool td_ready(const hb_ugks *H) { return H->has_case && !H->batch_owned && H->Wp && H->P.NT == 1; }
+
+int hb_ugks_td_step(hb_handle H, int nsteps)
+{
+    if (!H) return HB_EINVAL;
+    if (!td_ready(H)) return HB_ESTATE;
+    if (nsteps < 0) return HB_EINVAL;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    return td_steps(H, nsteps);
+}
+
+int hb_ugks_td_period(hb_handle H, int nsteps, double out[4])
+{
+    if (!H || !out) return HB_EINVAL;
+    if (!td_ready(H)) return HB_ESTATE;
+    if (nsteps < 1) return HB_EINVAL;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    const size_t wb = (size_t)H->P.nc * 4 * sizeof(double);
+    HIPOK(hipMemcpyAsync(H->Wp, H->W[H->cur], wb, hipMemcpyDeviceToDevice, H->stream));
+    const int rc = td_steps(H, nsteps);
+    if (rc != HB_OK) return rc;
+    hipLaunchKernelGGL(hb::k_period_diff, dim3(1), dim3(256), 0, H->stream, H->W[H->cur], H->Wp, H->P.nc, H->tdres);
+    HIPOK(hipGetLastError());
+    HIPOK(hipMemcpyAsync(out, H->tdres, 4 * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
+    int flag = 0;
+    HIPOK(hipMemcpy(&flag, H->flag, sizeof(int), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 4; k++)
+        if (!std::isfinite(out[k])) flag = 1;
+    return flag ? HB_EDIVERGED : HB_OK;
+}
+
+int hb_ugks_time(hb_handle H, double *t)
+{
+    if (!H || !t) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    *t = H->t_phys;
     return HB_OK;
 }
 
