@@ -8,7 +8,7 @@ HBM.  value = cell x velocity x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
                   [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
-                  [--only batch|serving]
+                  [--only batch|serving|hbtd] [--td-cap S]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -154,6 +154,96 @@ def serving(hb, hbcases, check_every=100, max_steps=20000, tol=1e-8):
     return out
 
 
+def td_step_size(hb, case):
+    """Physical step of the time-domain solver: the CFL bound of Eqs. (31)-(32)
+    without the spectral term, for gas at rest at T0 (the flows here stay
+    within 1e-3 of it), over every cell; rounded down so that one forcing
+    period holds a whole number of steps.  Returns (dt, steps per period)."""
+    import numpy as np
+    u, _ = hb.hb_vgrid_nodes(case.M, case.umax, case.vrule)
+    gamma = (case.K + 4.0) / (case.K + 2.0)
+    ut = max(abs(u[0]), abs(u[-1])) + np.sqrt(gamma / 2.0)
+    dx = np.diff(case.x_faces) if case.x_faces is not None else np.full(case.nx, case.L / case.nx)
+    dy = np.diff(case.y_faces) if case.y_faces is not None else np.full(case.ny, case.H / case.ny)
+    nu = ut / dx.min() + ut / dy.min()
+    period = 2.0 * np.pi / case.St
+    ns = int(np.ceil(period * nu / case.cfl))
+    return period / ns, ns
+
+
+def hb_vs_td(hb, hbcases, St, prec, cap_s, drop=7.0, hb_sample=100):
+    """Wall-clock to a `drop`-decade fall of the density residual (Eq. 43),
+    HB-UGKS (N_H = 1, local pseudo steps, residual sampled every hb_sample
+    steps) against the explicit time-domain UGKS (one level, global physical
+    step, period residual), both on the GPU from the same code, on the
+    paper's shear cavity (90 x 90 wall-refined cells, 28^2 Gauss-Hermite
+    velocities, Kn = 0.1).  Each clock starts at its first residual sample,
+    as the paper's shifted curves do; the unshifted totals are reported too.
+    The time-domain fundamental of U along the lid is taken over the last
+    period and compared with the HB one."""
+    import numpy as np
+    case = hbcases.shear_paper(St)
+    ua = case.walls[2][1]
+    out = {"workload": case.name, "St": St, "precision": "mixed" if prec == hb.HB_MIXED else "fp64",
+           "drop_decades": drop}
+    # HB
+    s = hb.Solver(case, precision=prec)
+    t0 = time.perf_counter()
+    k, r1, t1, hist = 0, None, None, []
+    while True:
+        s.step(hb_sample)
+        k += hb_sample
+        r = s.residual()[0]
+        t = time.perf_counter() - t0
+        if r1 is None:
+            r1, t1 = r, t
+        hist.append((k, t, r))
+        if k % (50 * hb_sample) == 0:
+            log(f"HB St {St}: step {k} R_rho {r:.3e} ({np.log10(r / r1):.2f} decades) {t:.1f} s")
+        if r <= r1 * 10.0 ** -drop or t > cap_s:
+            break
+    u_hb = 2.0 * abs(s.wall_harmonic(2, 1, 1)) / ua
+    out["hb"] = {"steps": k, "wall_s": t, "shifted_wall_s": t - t1, "R1": r1, "R_end": r,
+                 "reached": bool(r <= r1 * 10.0 ** -drop), "lid_U_amplitude": u_hb,
+                 "ms_per_step": 1e3 * t / k}
+    s.close()
+    log(f"HB St {St}: {k} steps, {t:.2f} s, lid U~ {u_hb:.5f}")
+    # time domain
+    dt, ns = td_step_size(hb, case)
+    tdc = case.with_(NH=0, dt_mode=1, dt_fixed=dt)
+    s = hb.Solver(tdc, precision=prec)
+    t0 = time.perf_counter()
+    p, r1, t1 = 0, None, None
+    while True:
+        r = s.td_period(ns)[0]
+        p += 1
+        t = time.perf_counter() - t0
+        if r1 is None:
+            r1, t1 = r, t
+        log(f"TD St {St}: period {p} ({ns} steps) R_rho {r:.3e} ({np.log10(r / r1):.2f} decades) {t:.1f} s")
+        if r <= r1 * 10.0 ** -drop or t > cap_s:
+            break
+    # fundamental of U in the lid-adjacent cells over one more period
+    top = (case.ny - 1) * case.nx + np.arange(case.nx)
+    ds = np.diff(case.x_faces)
+    acc = 0.0j
+    for j in range(ns):
+        s.td_step(1)
+        W = s.macro()[top, 0, :]
+        acc += np.sum(ds * W[:, 1] / W[:, 0]) / np.sum(ds) * np.exp(-1j * St * (p * ns + j + 1) * dt)
+    u_td = 2.0 * abs(acc / ns) / ua
+    out["td"] = {"dt": dt, "steps_per_period": ns, "periods": p, "steps": p * ns, "wall_s": t,
+                 "shifted_wall_s": t - t1, "R1": r1, "R_end": r, "reached": bool(r <= r1 * 10.0 ** -drop),
+                 "lid_U_amplitude": u_td, "ms_per_step": 1e3 * t / (p * ns)}
+    s.close()
+    out["speedup_shifted"] = out["td"]["shifted_wall_s"] / out["hb"]["shifted_wall_s"]
+    out["speedup_total"] = out["td"]["wall_s"] / out["hb"]["wall_s"]
+    out["lid_U_rel_diff"] = abs(u_hb - u_td) / u_td
+    log(f"TD St {St}: {p} periods, {t:.2f} s, lid U~ {u_td:.5f}; speedup {out['speedup_shifted']:.2f} "
+        f"(total {out['speedup_total']:.2f})")
+    return out
+
+
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -188,8 +278,11 @@ def main():
     ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
                     help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving"), default=None,
-                    help="run only the batched sweep or the serving measurement (prints its JSON)")
+    ap.add_argument("--only", choices=("batch", "serving", "hbtd"), default=None,
+                    help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
+                         "comparison (prints its JSON)")
+    ap.add_argument("--td-cap", type=float, default=600.0,
+                    help="hbtd: wall-clock cap (s) of each solver's run")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -226,6 +319,10 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
+    if args.only == "hbtd":
+        prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
+        print(json.dumps(hb_vs_td(hb, hbcases, args.st, prec, args.td_cap)), flush=True)
+        return
     if args.only:
         res = batched_sweep(hb, hbcases) if args.only == "batch" else serving(hb, hbcases)
         print(json.dumps(res), flush=True)

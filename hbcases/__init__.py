@@ -59,6 +59,7 @@ class Case:
     macro_mode: int = 0       # 0 = macro flux of Eq. (24); 1 = all-discrete sum of the micro flux
     dt_mode: int = 0          # 0 = local pseudo step (Eqs. 31-32); 1 = global step dt_fixed
     dt_fixed: float = 0.0
+    vrule: int = 0            # 1-D velocity rule: 0 = trapezoid on [-umax, umax], 1 = Gauss-Hermite
     name: str = field(default="", compare=False)
 
     @property
@@ -82,6 +83,32 @@ class Case:
         return replace(self, **kw)
 
 
+def stretched_faces(n, length, ds_min):
+    """n + 1 face coordinates on [0, length], refined symmetrically towards both
+    ends by a tanh law, x(s) = length/2 (1 + tanh(beta (2s - 1)) / tanh(beta)),
+    s = i/n, with beta chosen so that the first and last cells are ds_min wide.
+    (The paper refines its 90 x 90 cavity mesh to 0.001 H at every wall without
+    giving the law; this one is a choice.)"""
+    if not 0.0 < ds_min < length / n:
+        raise ValueError("ds_min must lie in (0, length/n)")
+
+    def first(beta):
+        return 0.5 * length * (1.0 + np.tanh(beta * (2.0 / n - 1.0)) / np.tanh(beta))
+
+    lo, hi = 1e-6, 50.0  # first() falls monotonically from ~length/n to 0 as beta grows
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if first(mid) > ds_min:
+            lo = mid
+        else:
+            hi = mid
+    beta = 0.5 * (lo + hi)
+    s = np.arange(n + 1) / n
+    x = 0.5 * length * (1.0 + np.tanh(beta * (2.0 * s - 1.0)) / np.tanh(beta))
+    x[0], x[-1] = 0.0, length
+    return tuple(float(v) for v in x)
+
+
 # ----------------------------------------------------------------- workloads
 def shear_small():
     """FP64 correctness case: 16x16 cells, 16x16 velocities on [-4,4], BGK,
@@ -93,6 +120,18 @@ def shear_cavity(Kn=1.0, St=1.0):
     """Benchmark case: 64x64 cells, 32x32 velocities on [-4,4], NH=1, lid 0.01, Shakhov."""
     return Case(64, 64, 32, 4.0, Kn, St, 1, lid_walls(0.01),
                 name=f"shear64_v32_nh1_kn{Kn:g}_st{St:g}")
+
+
+def shear_paper(St, Kn=0.1, A=1.0, NH=1, ny=90, ds_min=1e-3, M=28):
+    """The shear-driven cavity as the paper sets it up (Sec. 3.1): aspect
+    ratio A = L/H, ny = 90 cells refined to ds_min = 0.001 H at every wall
+    (nx = 90 A), lid U_a cos(omega t) with U_a = 0.0015, walls at T0, VSS
+    argon (omega 0.81, alpha 1, Shakhov Pr 2/3), 28 x 28 Gauss-Hermite
+    velocities (the rule it uses for Kn <= 0.1)."""
+    nx = int(round(ny * A))
+    return Case(nx, ny, M, 0.0, Kn, St, NH, lid_walls(0.0015), L=A,
+                x_faces=stretched_faces(nx, A, ds_min), y_faces=stretched_faces(ny, 1.0, ds_min),
+                vrule=1, name=f"shear_paper_{nx}x{ny}_gh{M}_nh{NH}_kn{Kn:g}_st{St:g}")
 
 
 SHEAR_KN = (0.01, 0.1, 1.0, 10.0)

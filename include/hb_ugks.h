@@ -22,7 +22,8 @@
  *     the null stream); calls that return host data synchronise that stream.
  * Host array layouts (row-major, last index fastest):
  *   W[c][n][4]  (rho, rho U, rho V, rho E), c = j*nx + i (x fastest)
- *   h, b[c][n][a]  a = iv*M + iu, node u_k = -umax + k*2*umax/(M-1)
+ *   h, b[c][n][a]  a = iv*M + iu, 1-D nodes u_k of the velocity rule
+ *                  (increasing k; hb_vgrid_nodes lists them)
  */
 #ifndef HB_UGKS_H
 #define HB_UGKS_H
@@ -71,12 +72,28 @@ typedef struct {
     double T_mean, T_hat_re, T_hat_im;
 } hb_wall;
 
-/* Square tensor velocity grid: m nodes per axis on [-umax, umax] with the
- * closed composite trapezoid rule (m even, 4 <= m <= 128). */
+/* 1-D velocity rules of Sec. 3.1.1 (the grid is their tensor product). */
+enum {
+    HB_RULE_TRAPEZOID = 0,      /* m equally spaced nodes on [-umax, umax], closed
+                                   composite trapezoid weights */
+    HB_RULE_GAUSS_HERMITE = 1   /* the m roots of the Hermite polynomial H_m (weight
+                                   exp(-u^2), the rest Maxwellian in these units),
+                                   weights multiplied by exp(u_k^2) so that sums
+                                   approximate plain integrals; umax is ignored and
+                                   the largest node takes its place in Eq. (32) */
+};
+
+/* Square tensor velocity grid: m nodes per axis (m even, 4 <= m <= 128). */
 typedef struct {
     int m;
     double umax;
+    int rule;                 /* HB_RULE_*; zero-initialised = trapezoid */
 } hb_vgrid;
+
+/* The 1-D nodes u[m] (increasing) and weights w[m] of a velocity rule; host
+ * only, no device needed.  Errors: HB_EINVAL (NULL, m odd or out of range,
+ * unknown rule, umax <= 0 for the trapezoid). */
+int hb_vgrid_nodes(const hb_vgrid *vg, double *u, double *w);
 
 typedef struct {
     double cfl;               /* Eq. (31); default 0.5 */
@@ -145,6 +162,16 @@ int hb_ugks_residual(hb_handle h, double out[4], long *step_index);
  * re/im layout [selected var in bit order][k][c]; capacity = doubles in each
  * of re and im.  Synchronises.  Errors: HB_ESTATE, HB_ECAPACITY, HB_EINVAL. */
 int hb_ugks_harmonics_out(hb_handle h, unsigned var_mask, double *re, double *im, size_t capacity);
+
+/* Wall average of one Fourier coefficient, as in the normalised lid
+ * amplitudes of Eqs. (41)-(42): <qhat_k>_wall = (1/L_w) sum_i qhat_k,i ds_i
+ * over the cells adjacent to the wall (0 bottom, 1 right, 2 top, 3 left), ds_i
+ * their width along it.  var numbers the variables as in
+ * hb_ugks_harmonics_out (0 rho ... 4 P_xy ... 6 q_y), 0 <= k <= NH; qhat_k is
+ * the coefficient of Eq. (40), so a real signal a cos(omega t) has
+ * |qhat_1| = a/2.  out[0] = Re, out[1] = Im.  Synchronises.
+ * Errors: HB_EINVAL, HB_ESTATE, HB_ENOMEM, HB_EDEVICE. */
+int hb_ugks_wall_harmonic(hb_handle h, int wall, int var, int k, double out[2]);
 
 /* Copy the state out / in (FP64, host layouts above; any pointer may be NULL
  * to skip that array).  capacity = doubles available in h (and in b); W needs

@@ -42,7 +42,7 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_double]
+                                  ctypes.c_double, _D, _D]
         L.hbref_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.hbref_td_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
         L.hbref_residual.argtypes = [ctypes.c_void_p, _D]
@@ -137,6 +137,22 @@ def equilibrium(K, Pr, prim, q, u, v):
     return H, B, Hp, Bp
 
 
+def gauss_hermite(M):
+    """M-point Gauss-Hermite rule for the weight exp(-u^2) (the velocity
+    quadrature of Sec. 3.1.1 for Kn <= 0.1), with the weight folded into the
+    returned weights, w_k exp(u_k^2), so that sum_k w_k f(u_k) approximates
+    the plain integral of f.  Nodes and Gauss weights from numpy."""
+    x, w = np.polynomial.hermite.hermgauss(int(M))
+    return np.ascontiguousarray(x), np.ascontiguousarray(w * np.exp(x * x))
+
+
+def velocity_rule(case):
+    """1-D nodes and weights of a case's velocity rule."""
+    if getattr(case, "vrule", 0) == 1:
+        return gauss_hermite(case.M)
+    return velocity_grid(case.M, case.umax)
+
+
 # ---------------------------------------------------------------- solver
 class Oracle:
     """One HB-UGKS case on the CPU (FP64).  ``case`` is an ``hbcases.Case``."""
@@ -149,10 +165,11 @@ class Oracle:
         yf = None if case.y_faces is None else np.ascontiguousarray(case.y_faces, np.float64)
         NH = 0 if td else case.NH
         dt_mode = 1 if td else case.dt_mode
+        u1, w1 = velocity_rule(case) if getattr(case, "vrule", 0) else (None, None)
         rc = lib().hbref_setup(self._h, case.nx, case.ny, case.L, case.H, _p(xf), _p(yf), case.M,
                                case.umax, case.Kn, case.St, NH, _p(walls), case.cfl,
                                case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K,
-                               case.macro_mode, dt_mode, case.dt_fixed)
+                               case.macro_mode, dt_mode, case.dt_fixed, _p(u1), _p(w1))
         if rc != 0:
             lib().hbref_free(self._h)
             self._h = None

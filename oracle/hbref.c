@@ -430,11 +430,13 @@ static void wall_state_at(const hbref *o, int wl, double theta, double *ut, doub
 /* walls: 4 x 6 doubles, wall order bottom (y=0), right (x=L), top (y=H),
  * left (x=0); per wall (ut_mean, ut_re, ut_im, T_mean, T_re, T_im), ut the
  * wall-tangential velocity along +x (bottom/top) or +y (left/right), T in T0.
- * dt_mode 0: local pseudo step of Eqs. (31)-(32); 1: one global step dt_fixed. */
+ * dt_mode 0: local pseudo step of Eqs. (31)-(32); 1: one global step dt_fixed.
+ * u1in, w1in: NULL for the closed trapezoid rule on [-umax, umax], else M
+ * increasing 1-D nodes and their weights (umax is then the last node). */
 int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, const double *yf, int M,
                 double umax, double Kn, double St, int NH, const double *walls, double cfl, int face_dt,
                 double Pr, double omega_vss, double alpha_vss, int K, int macro_mode, int dt_mode,
-                double dt_fixed)
+                double dt_fixed, const double *u1in, const double *w1in)
 {
     hbref *o = (hbref *)p;
     if (nx < 3 || ny < 3 || M < 2 || (M % 2) != 0 || NH < 0 || 2 * NH + 1 > NTMAX || Kn <= 0.0) return -1;
@@ -482,7 +484,13 @@ int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, 
 
     o->u1 = malloc(sizeof(double) * M);
     o->w1 = malloc(sizeof(double) * M);
-    hbref_velocity_grid(M, umax, o->u1, o->w1);
+    if (u1in && w1in) { /* a given 1-D rule (Gauss-Hermite, Sec. 3.1.1): its largest node bounds Eq. (32) */
+        memcpy(o->u1, u1in, sizeof(double) * M);
+        memcpy(o->w1, w1in, sizeof(double) * M);
+        o->umax = u1in[M - 1];
+    } else {
+        hbref_velocity_grid(M, umax, o->u1, o->w1);
+    }
     int nv = o->nv;
     o->u = malloc(sizeof(double) * nv);
     o->v = malloc(sizeof(double) * nv);

@@ -16,6 +16,7 @@ from . import build as _build
 
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_ESTATE, HB_EDIVERGED, HB_EDEVICE, HB_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 HB_FP64, HB_MIXED = 0, 1
+HB_RULE_TRAPEZOID, HB_RULE_GAUSS_HERMITE = 0, 1
 VARS = ("rho", "U", "V", "T", "Pxy", "qx", "qy")
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -37,7 +38,7 @@ class hb_wall(ctypes.Structure):
 
 
 class hb_vgrid(ctypes.Structure):
-    _fields_ = [("m", ctypes.c_int), ("umax", ctypes.c_double)]
+    _fields_ = [("m", ctypes.c_int), ("umax", ctypes.c_double), ("rule", ctypes.c_int)]
 
 
 class hb_numerics(ctypes.Structure):
@@ -58,8 +59,8 @@ class hb_result(ctypes.Structure):
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("bytes", ctypes.c_size_t)]
 
 
-EXPORTS = ("hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
-           "hb_ugks_td_step", "hb_ugks_td_period", "hb_ugks_time",
+EXPORTS = ("hb_vgrid_nodes", "hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
+           "hb_ugks_td_step", "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_wall_harmonic",
            "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
            "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
            "hb_ugks_destroy", "hb_ugks_strerror",
@@ -81,6 +82,8 @@ def load_library(path=None):
         raise RuntimeError(f"HIP library {p} is not built; run __graft_entry__.build()")
     L = ctypes.CDLL(p)
     vp, ip, dp, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.hb_vgrid_nodes.argtypes = [ctypes.POINTER(hb_vgrid), _D, _D]
+    L.hb_vgrid_nodes.restype = ctypes.c_int
     L.hb_ugks_default_numerics.argtypes = [ctypes.POINTER(hb_numerics)]
     L.hb_ugks_default_numerics.restype = None
     L.hb_ugks_create.argtypes = [ctypes.POINTER(hb_create_opts), ctypes.POINTER(vp)]
@@ -90,6 +93,7 @@ def load_library(path=None):
     L.hb_ugks_td_step.argtypes = [vp, ip]
     L.hb_ugks_td_period.argtypes = [vp, ip, _D]
     L.hb_ugks_time.argtypes = [vp, ctypes.POINTER(dp)]
+    L.hb_ugks_wall_harmonic.argtypes = [vp, ip, ip, ip, _D]
     L.hb_ugks_residual.argtypes = [vp, _D, ctypes.POINTER(ctypes.c_long)]
     L.hb_ugks_harmonics_out.argtypes = [vp, ctypes.c_uint, _D, _D, sz]
     L.hb_ugks_state_out.argtypes = [vp, _D, _D, _D, sz]
@@ -124,7 +128,7 @@ def load_library(path=None):
                                ctypes.POINTER(dp)]
     L.hb_serve_run.restype = ctypes.c_int
     for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_td_step",
-                 "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_residual",
+                 "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_wall_harmonic", "hb_ugks_residual",
                  "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
                  "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
                  "hb_batch_add", "hb_batch_remove", "hb_batch_set_active", "hb_batch_step", "hb_batch_residuals",
@@ -173,7 +177,7 @@ def _case_args(case):
     yf = None if case.y_faces is None else np.ascontiguousarray(case.y_faces, np.float64)
     g = hb_geometry(case.L, case.H, case.nx, case.ny, _dp(xf), _dp(yf))
     walls = (hb_wall * 4)(*[hb_wall(*map(float, w)) for w in case.walls])
-    vg = hb_vgrid(case.M, case.umax)
+    vg = hb_vgrid(case.M, case.umax, case.vrule)
     nm = hb_numerics(case.cfl, case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K, case.dt_mode,
                      case.dt_fixed)
     return g, walls, vg, nm, (xf, yf)
@@ -190,6 +194,15 @@ def hb_ugks_pseudo_step(h, nsteps):
     return _check(load_library().hb_ugks_pseudo_step(h, int(nsteps)), "hb_ugks_pseudo_step")
 
 
+def hb_vgrid_nodes(m, umax=4.0, rule=HB_RULE_TRAPEZOID):
+    """1-D nodes and weights of a velocity rule (host only)."""
+    u = np.zeros(m)
+    w = np.zeros(m)
+    vg = hb_vgrid(int(m), float(umax), int(rule))
+    _check(load_library().hb_vgrid_nodes(ctypes.byref(vg), _dp(u), _dp(w)), "hb_vgrid_nodes")
+    return u, w
+
+
 def hb_ugks_td_step(h, nsteps):
     return _check(load_library().hb_ugks_td_step(h, int(nsteps)), "hb_ugks_td_step")
 
@@ -204,6 +217,12 @@ def hb_ugks_time(h):
     t = ctypes.c_double()
     _check(load_library().hb_ugks_time(h, ctypes.byref(t)), "hb_ugks_time")
     return t.value
+
+
+def hb_ugks_wall_harmonic(h, wall, var, k):
+    out = np.zeros(2)
+    _check(load_library().hb_ugks_wall_harmonic(h, int(wall), int(var), int(k), _dp(out)), "hb_ugks_wall_harmonic")
+    return complex(out[0], out[1])
 
 
 def hb_ugks_residual(h):
@@ -303,6 +322,9 @@ class Solver:
     def time(self):
         return hb_ugks_time(self.h)
 
+    def wall_harmonic(self, wall, var, k=1):
+        return hb_ugks_wall_harmonic(self.h, wall, var, k)
+
     def residual(self):
         rc, r, k = hb_ugks_residual(self.h)
         _check(rc, "hb_ugks_residual")
@@ -313,6 +335,13 @@ class Solver:
 
     def state(self):
         return hb_ugks_state_out(self.h)
+
+    def macro(self):
+        """W[c][n][4] only (no distribution copy)."""
+        nx, ny, nc, M, nv, NT = self.sizes
+        W = np.zeros((nc, NT, 4))
+        _check(load_library().hb_ugks_state_out(self.h, _dp(W), None, None, 0), "hb_ugks_state_out")
+        return W
 
     def set_state(self, W, h, b):
         hb_ugks_state_in(self.h, W, h, b)

@@ -135,6 +135,7 @@ struct hb_ugks {
     int *bnd_cells = nullptr;
     std::vector<int> bnd_host;  // the boundary-ring cells (host copy, for batched work lists)
     std::vector<int> perm;      // natural alpha -> internal alpha'
+    std::vector<double> xf_host, yf_host;  // face coordinates (wall averages)
     // timing: one set of HB_NKERN + 1 events per timed step, read back lazily
     bool timing = false;
     std::vector<hipEvent_t> tev;

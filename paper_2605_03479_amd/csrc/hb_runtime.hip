@@ -7,6 +7,7 @@
 // residual, update) followed by a buffer swap.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -49,6 +50,82 @@ static int dalloc(hb_ugks *H, void **p, size_t nbytes)
     }
     H->bufs.push_back({*p, nbytes});
     H->bytes += nbytes;
+    return HB_OK;
+}
+
+// Orthonormal Hermite functions psi_k(x) = H_k(x) exp(-x^2/2) / sqrt(2^k k! sqrt(pi)),
+// k = n-1 and n, by their three-term recurrence (values stay O(1) for any x).
+static void hermite_fn(int n, double x, double &pm1, double &pn)
+{
+    double a = 0.0, b = std::pow(M_PI, -0.25) * std::exp(-0.5 * x * x);  // psi_{-1}, psi_0
+    for (int k = 0; k < n; k++) {
+        const double c = std::sqrt(2.0 / (k + 1)) * x * b - std::sqrt((double)k / (k + 1)) * a;
+        a = b;
+        b = c;
+    }
+    pm1 = a;
+    pn = b;
+}
+
+// 1-D velocity rule of Sec. 3.1.1.  Trapezoid: m equally spaced nodes on
+// [-umax, umax], closed composite trapezoid weights.  Gauss-Hermite: the m
+// roots x_k of H_m (the Maxwellian at rest in these units is exp(-u^2)/pi, the
+// weight the rule is exact for) with the weight folded back in,
+// w_k = 1 / (m psi_{m-1}(x_k)^2) = (Gauss weight) * exp(x_k^2), so that
+// sum_k w_k f(u_k) approximates the plain integral of f.  Positive roots are
+// bracketed by a scan finer than a tenth of the smallest root spacing
+// (about pi / sqrt(2 m)), then bisected to the last bit.
+static int velocity_rule(const hb_vgrid *vg, double *u, double *w)
+{
+    const int m = vg->m;
+    if (m < 4 || m > 128 || (m & 1)) return HB_EINVAL;
+    if (vg->rule == HB_RULE_TRAPEZOID) {
+        if (!(vg->umax > 0.0)) return HB_EINVAL;
+        const double du = 2.0 * vg->umax / (m - 1);
+        for (int k = 0; k < m; k++) {
+            u[k] = -vg->umax + k * du;
+            w[k] = (k == 0 || k == m - 1) ? 0.5 * du : du;
+        }
+        return HB_OK;
+    }
+    if (vg->rule != HB_RULE_GAUSS_HERMITE) return HB_EINVAL;
+    const int half = m / 2;
+    const double xend = std::sqrt(2.0 * m + 1.0) + 1.0, step = 0.1 * M_PI / std::sqrt(2.0 * m + 1.0);
+    int found = 0;
+    double pm1, p0, x0 = 0.0;
+    hermite_fn(m, x0, pm1, p0);
+    while (x0 < xend && found < half) {
+        double x1 = std::min(x0 + step, xend), p1;
+        hermite_fn(m, x1, pm1, p1);
+        if ((p0 < 0.0) != (p1 < 0.0)) {
+            double lo = x0, hi = x1, plo = p0;
+            for (int it = 0; it < 200 && hi - lo > 0.0; it++) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double q, pmid;
+                hermite_fn(m, mid, q, pmid);
+                if ((pmid < 0.0) == (plo < 0.0)) {
+                    lo = mid;
+                    plo = pmid;
+                } else {
+                    hi = mid;
+                }
+            }
+            const double r = 0.5 * (lo + hi);
+            double q, pr;
+            hermite_fn(m, r, q, pr);
+            u[half + found] = r;
+            w[half + found] = 1.0 / (m * q * q);
+            found++;
+        }
+        x0 = x1;
+        p0 = p1;
+    }
+    if (found != half) return HB_EINVAL;
+    for (int k = 0; k < half; k++) {
+        u[half - 1 - k] = -u[half + k];
+        w[half - 1 - k] = w[half + k];
+    }
     return HB_OK;
 }
 
@@ -158,6 +235,12 @@ const char *hb_ugks_strerror(int s)
     }
 }
 
+int hb_vgrid_nodes(const hb_vgrid *vg, double *u, double *w)
+{
+    if (!vg || !u || !w) return HB_EINVAL;
+    return velocity_rule(vg, u, w);
+}
+
 int hb_ugks_create(const hb_create_opts *opts, hb_handle *out)
 {
     if (!out) return HB_EINVAL;
@@ -203,7 +286,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     if (num) nm = *num;
     const int nx = g->nx, ny = g->ny, M = vg->m;
     if (nx < 3 || ny < 3 || M < 4 || M > 128 || (M & 1) || NH < 0 || 2 * NH + 1 > HB_NTMAX || !(Kn > 0.0) ||
-        !(St >= 0.0) || !(vg->umax > 0.0) || !(nm.cfl > 0.0) || nm.K_int < 0 || !(nm.Pr > 0.0) ||
+        !(St >= 0.0) || (vg->rule != HB_RULE_TRAPEZOID && vg->rule != HB_RULE_GAUSS_HERMITE) ||
+        (vg->rule == HB_RULE_TRAPEZOID && !(vg->umax > 0.0)) || !(nm.cfl > 0.0) || nm.K_int < 0 || !(nm.Pr > 0.0) ||
         (nm.dt_mode == 1 && !(nm.dt_fixed > 0.0)) || !(g->L > 0.0) || !(g->H > 0.0))
         return HB_EINVAL;
     for (int w = 0; w < 4; w++)
@@ -246,7 +330,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.Pr = nm.Pr;
     P.cfl = nm.cfl;
     P.gamma = (P.K + 4.0) / (P.K + 2.0);
-    P.umax = vg->umax;
+    P.umax = vg->umax;  // the Gauss-Hermite rule replaces it by its largest node below
     const int NT = P.NT;
     for (int n = 0; n < NT; n++)
         for (int m = 0; m < NT; m++) {
@@ -278,11 +362,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     }
     for (int i = 1; i < nx; i++) rcx[i] = 1.0 / (xc[i] - xc[i - 1]);
     for (int j = 1; j < ny; j++) rcy[j] = 1.0 / (yc[j] - yc[j - 1]);
-    const double du = 2.0 * vg->umax / (M - 1);
-    for (int k = 0; k < M; k++) {
-        u1[k] = -vg->umax + k * du;
-        w1[k] = (k == 0 || k == M - 1) ? 0.5 * du : du;
-    }
+    if (velocity_rule(vg, u1.data(), w1.data()) != HB_OK) return HB_EINVAL;
+    if (vg->rule == HB_RULE_GAUSS_HERMITE) P.umax = u1[M - 1];
     const size_t ox_xc = geo.size();
     geo.insert(geo.end(), xc.begin(), xc.end());
     const size_t ox_yc = geo.size();
@@ -362,12 +443,14 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->n_bnd = (int)bnd.size();
     H->n_int = P.nc - H->n_bnd;
     ALLOC(H->bnd_cells, bnd.size(), int);
-    if (NT == 1 && P.dt_mode == 1) {
+    if (NT == 1 && P.dt_mode == 1 && !H->pool) {
         ALLOC(H->Wp, (size_t)P.nc * 4, double);
         ALLOC(H->tdres, 4, double);
     }
 #undef ALLOC
     H->bnd_host = bnd;
+    H->xf_host = xf;
+    H->yf_host = yf;
     if (H->count_only) return HB_OK;
     HIPOK(hipMemcpy(H->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -701,6 +784,32 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
         std::memcpy(im + o, him.data() + v * per, per * sizeof(double));
         o += per;
     }
+    return HB_OK;
+}
+
+int hb_ugks_wall_harmonic(hb_handle H, int wall, int var, int k, double out[2])
+{
+    if (!H || !out || wall < 0 || wall > 3 || var < 0 || var > 6 || k < 0) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    const hb::Params &P = H->P;
+    if (k > P.NH) return HB_EINVAL;
+    const size_t per = (size_t)(P.NH + 1) * P.nc;
+    std::vector<double> re(per), im(per);
+    const int rc = hb_ugks_harmonics_out(H, 1u << var, re.data(), im.data(), per);
+    if (rc != HB_OK) return rc;
+    const bool horiz = wall == 0 || wall == 2;  // bottom/top run along x
+    const int n = horiz ? P.nx : P.ny;
+    const std::vector<double> &f = horiz ? H->xf_host : H->yf_host;
+    double sr = 0.0, si = 0.0;
+    for (int i = 0; i < n; i++) {
+        const int c = wall == 0 ? i : wall == 2 ? (P.ny - 1) * P.nx + i : wall == 1 ? i * P.nx + P.nx - 1 : i * P.nx;
+        const double ds = f[i + 1] - f[i];
+        sr += re[(size_t)k * P.nc + c] * ds;
+        si += im[(size_t)k * P.nc + c] * ds;
+    }
+    const double len = f[n] - f[0];
+    out[0] = sr / len;
+    out[1] = si / len;
     return HB_OK;
 }
 

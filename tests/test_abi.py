@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "hb_ugks.h")).read()
-    return sorted(set(re.findall(r"\b(hb_(?:ugks|batch|serve)_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(hb_(?:ugks|batch|serve|vgrid)_\w+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -71,3 +71,30 @@ def test_create_bad_precision_or_device(lib):
     assert lib.hb_ugks_create(ctypes.byref(o), ctypes.byref(h)) == hb.HB_EINVAL
     o = hb.hb_create_opts(4096, None, 0, 0)
     assert lib.hb_ugks_create(ctypes.byref(o), ctypes.byref(h)) == hb.HB_EDEVICE
+
+
+def test_vgrid_nodes_host(lib, oracle_mod):
+    """Velocity rules of the library (host only): the trapezoid nodes and
+    weights equal the oracle's; the Gauss-Hermite rule is exact for
+    exp(-u^2) u^(2j), j < m (closed form Gamma(j + 1/2)) and matches the
+    oracle's independent rule; bad arguments are refused."""
+    import mpmath as mp
+    import numpy as np
+    u, w = hb.hb_vgrid_nodes(16, 4.0, hb.HB_RULE_TRAPEZOID)
+    uo, wo = oracle_mod.velocity_grid(16, 4.0)
+    np.testing.assert_allclose(u, uo, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, wo, rtol=0, atol=1e-15)
+    for m in (4, 28, 64, 128):
+        u, w = hb.hb_vgrid_nodes(m, 0.0, hb.HB_RULE_GAUSS_HERMITE)
+        assert np.all(np.diff(u) > 0) and np.all(w > 0)
+        g = w * np.exp(-u * u)
+        for j in range(min(m, 40)):
+            ref = float(mp.gamma(j + 0.5))
+            assert abs(np.sum(g * u ** (2 * j)) - ref) <= 1e-12 * ref * max(1.0, 2.0 ** j), (m, j)
+        if m <= 64:
+            uo, wo = oracle_mod.gauss_hermite(m)
+            np.testing.assert_allclose(u, uo, rtol=0, atol=1e-13 * np.max(np.abs(uo)))
+            np.testing.assert_allclose(w, wo, rtol=1e-11)
+    for m, umax, rule in ((5, 4.0, 0), (2, 4.0, 1), (16, 0.0, 0), (16, 4.0, 7)):
+        with pytest.raises(hb.HBError):
+            hb.hb_vgrid_nodes(m, umax, rule)

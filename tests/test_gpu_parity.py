@@ -193,3 +193,24 @@ def test_full_size_one_step(gpu, oracle_mod):
     rest, out = _run_pair(gpu, oracle_mod, case, st, [1])
     for k, sg, so, rg, ro in out:
         _compare_states(sg, so, rest, what=f"64x64 step {k}")
+
+
+@pytest.mark.parametrize("prec,tol", [(0, TOL), (1, 1e-6)], ids=["fp64", "mixed"])
+def test_gauss_hermite_grid(gpu, oracle_mod, prec, tol):
+    """The Gauss-Hermite velocity rule of Sec. 3.1.1 (14 nodes per axis, up to
+    |u| = 4.30): the library computes its own nodes, the oracle takes
+    numpy's; every element after 1 and 6 steps."""
+    case = Case(7, 6, 14, 0.0, 0.1, 2.0, 1, hbcases.lid_walls(0.02), vrule=1, name="gh14")
+    st = _perturbed(oracle_mod, case, 313)
+    o = oracle_mod.Oracle(case)
+    o.set_state(*st)
+    s = gpu.Solver(case, precision=prec)
+    s.set_state(*st)
+    rest = _rest_like(o.state())
+    done = 0
+    for k in (1, 6):
+        o.step(k - done)
+        s.step(k - done)
+        done = k
+        _compare_states(s.state(), o.state(), rest, tol=tol, what=f"GH prec {prec} step {k}")
+    s.close()

@@ -15,13 +15,15 @@ def _wide(**kw):
     return Case(**base)
 
 
-@pytest.mark.parametrize("Kn,St,NH,Pr", [(0.01, 1.0, 1, 2 / 3), (1.0, 3.0, 2, 1.0),
-                                         (10.0, 0.3, 3, 2 / 3), (0.1, 10.0, 0, 2 / 3)])
-def test_resting_maxwellian_is_fixed_point(oracle_mod, Kn, St, NH, Pr):
+@pytest.mark.parametrize("Kn,St,NH,Pr,vrule", [(0.01, 1.0, 1, 2 / 3, 0), (1.0, 3.0, 2, 1.0, 0),
+                                               (10.0, 0.3, 3, 2 / 3, 0), (0.1, 10.0, 0, 2 / 3, 0),
+                                               (0.1, 2.0, 1, 2 / 3, 1)])
+def test_resting_maxwellian_is_fixed_point(oracle_mod, Kn, St, NH, Pr, vrule):
     """A uniform rest Maxwellian between stationary walls at T0 stays at rest:
     every flux cancels, the spectral source vanishes, collisions are in
-    equilibrium (Sec. 2.4; Eqs. 27-29)."""
-    o = oracle_mod.Oracle(_wide(Kn=Kn, St=St, NH=NH, Pr=Pr))
+    equilibrium (Sec. 2.4; Eqs. 27-29).  vrule 1: the 28-point Gauss-Hermite
+    grid of Sec. 3.1.1, exact for the rest Maxwellian's moments."""
+    o = oracle_mod.Oracle(_wide(Kn=Kn, St=St, NH=NH, Pr=Pr, vrule=vrule))
     W0, h0, b0 = o.state()
     for _ in range(3):
         o.step(20)

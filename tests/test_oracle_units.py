@@ -238,3 +238,34 @@ def test_velocity_grid_trapezoid(oracle_mod):
     np.testing.assert_allclose(w1[1:-1], h, atol=1e-15)
     np.testing.assert_allclose(w1[[0, -1]], h / 2, atol=1e-15)
     np.testing.assert_allclose(u1, -u1[::-1], atol=1e-15)
+
+
+@pytest.mark.parametrize("M", [4, 16, 28, 64])
+def test_gauss_hermite_moments(oracle_mod, M):
+    """The M-point Gauss-Hermite rule (Sec. 3.1.1) is exact for polynomials of
+    degree <= 2M - 1 against exp(-u^2): with the weight folded into w,
+    sum w u^(2j) exp(-u^2) = Gamma(j + 1/2) and odd moments vanish.  A wrong
+    node, a weight without the exp(u^2) factor or a mirrored half fails."""
+    u, w = oracle_mod.gauss_hermite(M)
+    assert np.all(np.diff(u) > 0) and np.all(w > 0)
+    np.testing.assert_allclose(u, -u[::-1], atol=1e-14)
+    g = w * np.exp(-u * u)
+    for j in range(M):
+        ref = float(mp.gamma(j + 0.5))
+        assert abs(np.sum(g * u ** (2 * j)) - ref) <= 1e-13 * ref * max(1.0, 2.0 ** j), j
+        assert abs(np.sum(g * u ** (2 * j + 1))) <= 1e-13 * ref * max(1.0, 2.0 ** j)
+
+
+def test_gauss_hermite_rest_state_moments(oracle_mod):
+    """On the 28 x 28 Gauss-Hermite grid the oracle's rest Maxwellian has
+    density 1 and energy (2 + K)/4 to round-off (the rule is exact for it)."""
+    import hbcases
+    case = hbcases.Case(4, 4, 28, 0.0, 0.1, 1.0, 0, vrule=1)
+    o = oracle_mod.Oracle(case)
+    W, h, b = o.state()
+    u, w1 = oracle_mod.gauss_hermite(28)
+    uu, vv = np.meshgrid(u, u)
+    w = np.outer(w1, w1).ravel()
+    e2 = (uu * uu + vv * vv).ravel()
+    np.testing.assert_allclose(np.sum(w * h[0, 0]), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(0.5 * np.sum(w * (e2 * h[0, 0] + b[0, 0])), (2 + case.K) / 4.0, rtol=1e-14)
