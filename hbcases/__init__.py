@@ -134,6 +134,18 @@ def shear_paper(St, Kn=0.1, A=1.0, NH=1, ny=90, ds_min=1e-3, M=28):
                 vrule=1, name=f"shear_paper_{nx}x{ny}_gh{M}_nh{NH}_kn{Kn:g}_st{St:g}")
 
 
+def thermal_paper(St, Kn=0.1, NH=2, ny=90, ds_min=1e-3, M=28):
+    """The thermally driven cavity as the paper sets it up (Sec. 3.2): the
+    mesh of the shear case, top wall T = T0 (1 + 0.3 cos(omega t)), other
+    walls at T0, all at rest, N_H = 2, 28 x 28 Gauss-Hermite velocities.
+    (Kn of its timing runs is not stated; Kn = 0.1 is the reading.)"""
+    w = [list(r) for r in REST_WALLS]
+    w[2][4] = 0.3
+    f = stretched_faces(ny, 1.0, ds_min)
+    return Case(ny, ny, M, 0.0, Kn, St, NH, tuple(tuple(r) for r in w), x_faces=f, y_faces=f, vrule=1,
+                name=f"thermal_paper_{ny}x{ny}_gh{M}_nh{NH}_kn{Kn:g}_st{St:g}")
+
+
 SHEAR_KN = (0.01, 0.1, 1.0, 10.0)
 SHEAR_ST = (0.1, 1.0, 10.0)
 
