@@ -30,14 +30,14 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "f71dadb2de6000cf",
+    "sources_sha256_16": "fcab544846b05bfe",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 608286685,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 1062290028,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 166358268,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 2079932765,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 3862149058,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 811674084,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 608296597,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 1065146733,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 166290128,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 2080300124,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 3972816182,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 822294584,
     },
 }
 

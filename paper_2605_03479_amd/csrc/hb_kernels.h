@@ -169,7 +169,9 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
             acc[53] += wm[1] * bc;
             acc[54] += wm[2] * bc;
         }
-        // wave reduction in two halves through LDS: lane k sums row k
+        // wave reduction in two halves through LDS: lane k sums row k.  Each
+        // wave works in its own rows, so a wave-level fence orders the writes
+        // before the reads; only the quadrant combine below needs the block.
         double *rb = red[q];
 #pragma unroll
         for (int half = 0; half < 2; half++) {
@@ -177,7 +179,8 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
 #pragma unroll
             for (int k = 0; k < 28; k++)
                 if (k < kn) rb[k * K1_ROW + lane] = acc[k0 + k];
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             if (lane < kn) {
                 const double2 *row = reinterpret_cast<const double2 *>(rb + lane * K1_ROW);
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -191,7 +194,8 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
                 }
                 wsum[q][k0 + lane] = (s0 + s1) + (s2 + s3);
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
         // combine quadrants: E = q1 + q3, W = q0 + q2, N = q2 + q3, S = q0 + q1
@@ -679,10 +683,29 @@ __global__ __launch_bounds__(256) void k_period_diff(const double *__restrict__ 
 // tables of the four faces (merged normal table + one tangential table per
 // upwind side) and of the cell equilibria at k and k+1, for every level.
 
+// a * b + c with c wave-uniform, as one VOP3 FMA reading c from scalar
+// registers.  (Left to itself the compiler copies c into a vector register
+// and uses the accumulating form: two extra moves per FP64 coefficient.)
+__device__ inline double fma_s(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+// Cubic c0 + c1 n + c2 t + c3 n^2 + c4 n t + c5 t^2 + c6 n^3 + c7 n^2 t + c8 n t^2
+// + c9 t^3 in nested form, every step pairing one wave-uniform coefficient
+// with per-lane values.
 template <typename Ptr>
 __device__ inline double p3_eval(Ptr c, double n, double t)
 {
-    return c[0] + n * (c[1] + n * (c[3] + n * c[6]) + t * (c[4] + n * c[7])) + t * (c[2] + t * (c[5] + t * c[9] + n * c[8]));
+#pragma clang fp contract(off)
+    const double a = n * c[6] + c[3];
+    const double b = n * c[7] + c[4];
+    const double d = __builtin_fma(t, c[9], n * c[8]);
+    const double e = __builtin_fma(t, b, fma_s(n, a, c[1]));
+    const double f = fma_s(t, d + c[5], c[2]);
+    return __builtin_fma(t, f, fma_s(n, e, c[0]));
 }
 
 // Read-only data every lane of the wave reads at the same address: typed in
