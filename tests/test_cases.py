@@ -1,0 +1,26 @@
+"""Host checks of the case builders (no GPU): the wall-refined mesh law and
+the paper's cavity setups."""
+import numpy as np
+
+import hbcases
+
+
+def test_stretched_faces():
+    for n, L, ds in ((90, 1.0, 1e-3), (180, 2.0, 1e-3), (45, 0.5, 1e-3), (9, 1.0, 0.03)):
+        x = np.array(hbcases.stretched_faces(n, L, ds))
+        d = np.diff(x)
+        assert len(x) == n + 1 and x[0] == 0.0 and x[-1] == L
+        assert np.all(d > 0)
+        np.testing.assert_allclose([d[0], d[-1]], ds, rtol=1e-9)
+        np.testing.assert_allclose(d, d[::-1], rtol=1e-9)  # symmetric about the centre
+        h = n // 2
+        assert np.all(np.diff(d[:h]) > 0)  # cells grow towards the centre
+
+
+def test_paper_cases():
+    c = hbcases.shear_paper(30.0, Kn=0.1, A=2.0)
+    assert (c.nx, c.ny, c.M, c.NH, c.vrule) == (180, 90, 28, 1, 1)
+    assert c.L == 2.0 and c.walls[2][1] == 0.0015 and c.omega_vss == 0.81
+    t = hbcases.thermal_paper(2.0)
+    assert (t.nx, t.ny, t.NH) == (90, 90, 2) and t.walls[2][3:] == (1.0, 0.3, 0.0)
+    assert all(w[:3] == (0.0, 0.0, 0.0) for w in t.walls)
