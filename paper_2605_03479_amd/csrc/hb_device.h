@@ -76,7 +76,7 @@ __device__ inline void ccoef(double tau, double dG, double C[5])
         double sgn = 1.0;  // (-1)^(k+1) at k = 3
 #pragma unroll
         for (int k = 3; k <= 30; k++) {
-            t *= x / k;
+            t *= x * (1.0 / k);  // unrolled: 1/k is a constant, no division in the chain
             p3 += sgn * t;
             p2 += sgn * (2.0 - k) * t;
             p5 += sgn * (k - 1.0) * t;
@@ -101,11 +101,12 @@ __device__ inline void ccoef(double tau, double dG, double C[5])
 // mean (Un, Ut), inverse temperature lam, K internal dofs.
 __device__ inline void slope_solve(double Un, double Ut, double lam, int K, const double dw[4], double a[4])
 {
-    double s = Un * Un + Ut * Ut + (K + 2.0) / (2.0 * lam);
+    const double rk = 1.0 / (K + 2.0);
+    double s = Un * Un + Ut * Ut + 0.5 * (K + 2.0) / lam;
     double R2 = dw[1] - Un * dw[0];
     double R3 = dw[2] - Ut * dw[0];
     double R4 = 2.0 * dw[3] - s * dw[0];
-    double a4 = 4.0 * lam * lam * (R4 - 2.0 * Un * R2 - 2.0 * Ut * R3) / (K + 2.0);
+    double a4 = 4.0 * lam * lam * (R4 - 2.0 * Un * R2 - 2.0 * Ut * R3) * rk;
     double a2 = 2.0 * lam * R2 - Un * a4;
     double a3 = 2.0 * lam * R3 - Ut * a4;
     a[0] = dw[0] - Un * a2 - Ut * a3 - 0.5 * a4 * s;

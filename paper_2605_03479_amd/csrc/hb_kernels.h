@@ -110,23 +110,55 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     const long oW = mx == 1 ? 0 : -sx, oE = mx == 2 ? 0 : sx, oS = my == 1 ? 0 : -sy, oN = my == 2 ? 0 : sy;
     const double rxm = G(P.rcx)[i], rxp = G(P.rcx)[i + 1], rym = G(P.rcy)[j], ryp = G(P.rcy)[j + 1];
 
+    // One lane's stencil values and velocity for (level n, quadrant row r).
+    struct Ld {
+        double hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, u, v, w;
+    };
+    auto load = [&](int n, int r) {
+        Ld d;
+        const int ap = q * P.Qp + r;
+        d.u = G(P.vu)[ap];
+        d.v = G(P.vv)[ap];
+        d.w = G(P.vw)[ap];
+        const long e = ((long)c * NT + n) * P.ls + ap;
+        const TS *hp = h + e, *bp = b + e;
+        const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
+        d.hc = ldv<TS>(hp, 0, rh);
+        d.bc = ldv<TS>(bp, 0, rb);
+        d.hW = ldv<TS>(hp, oW, rh);
+        d.bW = ldv<TS>(bp, oW, rb);
+        d.hE = ldv<TS>(hp, oE, rh);
+        d.bE = ldv<TS>(bp, oE, rb);
+        d.hS = ldv<TS>(hp, oS, rh);
+        d.bS = ldv<TS>(bp, oS, rb);
+        d.hN = ldv<TS>(hp, oN, rh);
+        d.bN = ldv<TS>(bp, oN, rb);
+        return d;
+    };
+    // (level, row) pairs in order.  With FP64 storage the loads of the next
+    // pair are issued before the arithmetic (and the level's reduction) of the
+    // current one; the mixed form measured no gain from it, so it loads in place.
+    constexpr bool PIPE = sizeof(TS) == 8;
+    const int nch = P.Qp / 64;
+    Ld nxt{};
+    if constexpr (PIPE) nxt = load(0, lane);
     for (int n = 0; n < NT; n++) {
         double acc[NMOM];
 #pragma unroll
         for (int k = 0; k < NMOM; k++) acc[k] = 0.0;
-        for (int r = lane; r < P.Qp; r += 64) {
-            const int ap = q * P.Qp + r;
-            const double u = G(P.vu)[ap], v = G(P.vv)[ap], w = G(P.vw)[ap];
-            const long e = ((long)c * NT + n) * P.ls + ap;
-            const TS *hp = h + e, *bp = b + e;
-            const double rh = href_of<TS>(P, ap), rb = 0.5 * P.K * rh;
-            const double hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
-            const double hW = ldv<TS>(hp, oW, rh), bW = ldv<TS>(bp, oW, rb);
-            const double hE = ldv<TS>(hp, oE, rh), bE = ldv<TS>(bp, oE, rb);
-            const double hS = ldv<TS>(hp, oS, rh), bS = ldv<TS>(bp, oS, rb);
-            const double hN = ldv<TS>(hp, oN, rh), bN = ldv<TS>(bp, oN, rb);
-            const double sxh = slope_c(hW, hc, hE, mx, rxm, rxp), sxb = slope_c(bW, bc, bE, mx, rxm, rxp);
-            const double syh = slope_c(hS, hc, hN, my, rym, ryp), syb = slope_c(bS, bc, bN, my, rym, ryp);
+        for (int ch = 0; ch < nch; ch++) {
+            Ld d;
+            if constexpr (PIPE) {
+                d = nxt;
+                const int nn = ch + 1 < nch ? n : n + 1, rr = ch + 1 < nch ? lane + 64 * (ch + 1) : lane;
+                if (nn < NT) nxt = load(nn, rr);
+            } else {
+                d = load(n, lane + 64 * ch);
+            }
+            const double u = d.u, v = d.v, w = d.w;
+            const double hc = d.hc, bc = d.bc;
+            const double sxh = slope_c(d.hW, hc, d.hE, mx, rxm, rxp), sxb = slope_c(d.bW, bc, d.bE, mx, rxm, rxp);
+            const double syh = slope_c(d.hS, hc, d.hN, my, rym, ryp), syb = slope_c(d.bS, bc, d.bN, my, rym, ryp);
             const double uu = u * u, uv = u * v, vv = v * v;
             const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
                                    w * vv * v};
@@ -368,10 +400,12 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         }
         double dWL[4], dWR[4], dWt[4];
         const double dL = xF - xL, dR = xR - xF;
+        // reciprocals once, products below (the divisions sat on the chain)
+        const double rrho = 1.0 / rho, rLr = rrho / dL, rRr = rrho / dR, rdG = 1.0 / dGf;
         for (int k = 0; k < 4; k++) {
-            dWL[k] = (fs.W[k] - WL[k]) / dL / rho;
-            dWR[k] = (WR[k] - fs.W[k]) / dR / rho;
-            dWt[k] = ts[k] / rho;
+            dWL[k] = (fs.W[k] - WL[k]) * rLr;
+            dWR[k] = (WR[k] - fs.W[k]) * rRr;
+            dWt[k] = ts[k] * rrho;
         }
         double aL[4], aR[4], at[4], A[4];
         slope_solve(Un, Ut, lam, K, dWL, aL);
@@ -407,8 +441,8 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
         for (int k = 0; k < 4; k++)
             F[k] = (C[0] * S1[k] + C[1] * rho * (c2a[k] + c2b[k] + c2c[k]) + C[2] * rho * c3[k] + C[3] * S4[k] +
-                    C[4] * c5s[k]) /
-                   dGf;
+                    C[4] * c5s[k]) *
+                   rdG;
         // micro-flux records: side 1 (u_n > 0) uses a^L, side 0 uses a^R
         const double xh = K / (2.0 * lam), xb = (K + 2.0) / (2.0 * lam);
         const double ln[3] = {0.0, 1.0, 0.0}, lt[3] = {0.0, 0.0, 1.0}, l1[3] = {1.0, 0.0, 0.0};
@@ -440,12 +474,12 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
             p3_axpy(C[1], nSb, Qb);
             p3_axpy(C[1], tTb, Qb);
             p3_axpy(C[2], pAb, Qb);
-            const double sh = pref / dGf, sbq = pref * xh / dGf;
+            const double sh = pref * rdG, sbq = pref * xh * rdG;
             for (int k = 0; k < 10; k++) {
                 Qh.c[k] *= sh;
                 Qb.c[k] *= sbq;
             }
-            store_side(rec, side, lam, Un, Ut, Qh, Qb, C[3] / dGf, C[4] / dGf);
+            store_side(rec, side, lam, Un, Ut, Qh, Qb, C[3] * rdG, C[4] * rdG);
         }
     } else {
         // ---------------- diffuse isothermal wall (Eqs. 25-28)
