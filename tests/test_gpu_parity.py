@@ -214,3 +214,19 @@ def test_gauss_hermite_grid(gpu, oracle_mod, prec, tol):
         done = k
         _compare_states(s.state(), o.state(), rest, tol=tol, what=f"GH prec {prec} step {k}")
     s.close()
+
+
+@pytest.mark.parametrize("nx,ny,M,NH", [(3, 3, 4, 0), (4, 3, 6, 5), (5, 5, 4, 3), (3, 6, 8, 1)])
+def test_degenerate_sizes(gpu, oracle_mod, nx, ny, M, NH):
+    """The smallest grids (every cell in the boundary ring, or one interior
+    cell), the smallest velocity grids (4 or 9 velocities per quadrant, padded
+    to 64 lanes) and the most levels (N_T = 11), forced by a lid, a sliding
+    wall and a heated wall, against the oracle after 1 and 7 steps."""
+    w = [list(r) for r in hbcases.lid_walls(0.03)]
+    w[0][4] = 0.1
+    w[1][2] = 0.02
+    case = Case(nx, ny, M, 4.0, 0.5, 2.0, NH, tuple(map(tuple, w)))
+    st = _perturbed(oracle_mod, case, 900 + nx * 10 + ny)
+    rest, out = _run_pair(gpu, oracle_mod, case, st, [1, 7])
+    for k, sg, so, rg, ro in out:
+        _compare_states(sg, so, rest, what=f"{nx}x{ny} M={M} NH={NH} step {k}")
