@@ -46,6 +46,10 @@ def test_null_and_state_errors(lib):
     assert lib.hb_ugks_set_case(None, None, 1.0, 1.0, 1, None, None, None) == hb.HB_EINVAL
     out = (ctypes.c_double * 4)()
     assert lib.hb_ugks_residual(None, out, None) == hb.HB_EINVAL
+    assert lib.hb_ugks_td_step(None, 1) == hb.HB_EINVAL
+    assert lib.hb_ugks_td_period(None, 1, out) == hb.HB_EINVAL
+    assert lib.hb_ugks_time(None, ctypes.byref(ctypes.c_double())) == hb.HB_EINVAL
+    assert lib.hb_ugks_wall_harmonic(None, 2, 1, 1, out) == hb.HB_EINVAL
     lib.hb_ugks_destroy(None)  # no-op
 
 
