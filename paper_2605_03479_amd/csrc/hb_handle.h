@@ -13,7 +13,7 @@
 #include "hb_ugks.h"
 
 constexpr int HB_RING = 1024;  // residual ring entries per case
-constexpr int HB_NKERN = 7;    // kernels of one pseudo step, in launch order
+constexpr int HB_NKERN = 6;    // kernels of one pseudo step, in launch order
 
 struct HbBuf {
     void *p = nullptr;

@@ -302,6 +302,28 @@ __device__ inline void gsums(const Params &P, double lam, double U, int sel, dou
     }
 }
 
+// Two full-range sums of gsums at once (normal and tangential mean of one
+// Maxwellian): the exponentials of both, and of four nodes, are independent,
+// which a one-thread-per-face kernel needs to keep its pipeline busy.  Each
+// sum still accumulates in node order.
+__device__ inline void gsums2(const Params &P, double lam, double Un, double Ut, double Gn[7], double Gt[7])
+{
+#pragma unroll
+    for (int k = 0; k < 7; k++) Gn[k] = Gt[k] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < P.M; k++) {
+        const double x = P.u1[k], w = P.w1[k];
+        double tn = w * exp(-lam * (x - Un) * (x - Un)), tt = w * exp(-lam * (x - Ut) * (x - Ut));
+#pragma unroll
+        for (int p = 0; p < 7; p++) {
+            Gn[p] += tn;
+            Gt[p] += tt;
+            tn *= x;
+            tt *= x;
+        }
+    }
+}
+
 // sum_alpha w u_n psi (H0 + H0+, B0 + B0+) from the 1-D sums of the face Maxwellian.
 __device__ inline void equil_flux_sums(int K, double pref, double lam, const P3 &Ph, const P3 &Pb, const double *Gn,
                                        const double *Gt, double S[4])
@@ -440,8 +462,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         Ph.c[0] += 1.0;
         Pb.c[0] += 1.0;
         double Gn[7], Gt[7];
-        gsums(P, lam, Un, 0, Gn);
-        gsums(P, lam, Ut, 0, Gt);
+        gsums2(P, lam, Un, Ut, Gn, Gt);
         const double pref = rho * lam / HB_PI;
         double S1[4];
         equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
@@ -1218,6 +1239,19 @@ __device__ inline void dt_thread(const Params &P, const double *W, double *dtc, 
 __global__ void k_dt(Params P, const double *W, double *dtc)
 {
     dt_thread(P, W, dtc, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The next local steps and the residual of the step in one launch: blocks
+// 0 .. gridDim.x - 2 take 256 cells each, the last block the residual sum
+// (two tiny kernels cost mostly their launch).
+__global__ __launch_bounds__(256) void k_dt_resid(Params P, const double *__restrict__ W, double *__restrict__ dtc,
+                                                  const double *__restrict__ rpart, int nblk, double *__restrict__ ring,
+                                                  int slot, int *__restrict__ flag)
+{
+    if (blockIdx.x + 1 < gridDim.x)
+        dt_thread(P, W, dtc, blockIdx.x * 256 + threadIdx.x);
+    else
+        resid_block(rpart, nblk, P.nc, ring, slot, flag);
 }
 
 // ---------------------------------------------------------------- harmonics

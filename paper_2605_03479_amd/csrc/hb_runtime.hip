@@ -19,7 +19,7 @@
 #include "hb_handle.h"
 
 namespace {
-const char *KNAMES[HB_NKERN] = {"moments", "faces", "cells", "local_dt", "residual", "update_int", "update_bnd"};
+const char *KNAMES[HB_NKERN] = {"moments", "faces", "cells", "dt_resid", "update_int", "update_bnd"};
 }
 
 static void free_case(hb_ugks *H)
@@ -533,13 +533,11 @@ static int enqueue_step(hb_ugks *H)
     hipLaunchKernelGGL(hb::k_cells, dim3(H->cells_blocks), dim3(128), 0, H->stream, P, H->feed, H->recx, H->recy,
                        H->W[c], H->dt[c], H->W[x], H->crec, H->rpart);
     if (ev) HIPOK(hipEventRecord(ev[3], H->stream));
-    hipLaunchKernelGGL(hb::k_dt, dim3((P.nc + 127) / 128), dim3(128), 0, H->stream, P, H->W[x], H->dt[x]);
+    hipLaunchKernelGGL(hb::k_dt_resid, dim3((P.nc + 255) / 256 + 1), dim3(256), 0, H->stream, P, H->W[x], H->dt[x],
+                       H->rpart, H->cells_blocks, H->ring, slot, H->flag);
     if (ev) HIPOK(hipEventRecord(ev[4], H->stream));
-    hipLaunchKernelGGL(hb::k_resid, dim3(1), dim3(256), 0, H->stream, H->rpart, H->cells_blocks, P.nc, H->ring, slot,
-                       H->flag);
-    if (ev) HIPOK(hipEventRecord(ev[5], H->stream));
-    launch_update(H, P, c, x, ev ? ev[6] : nullptr);
-    if (ev) HIPOK(hipEventRecord(ev[7], H->stream));
+    launch_update(H, P, c, x, ev ? ev[5] : nullptr);
+    if (ev) HIPOK(hipEventRecord(ev[6], H->stream));
     HIPOK(hipGetLastError());
     H->cur = x;
     H->step++;
