@@ -8,7 +8,7 @@ HBM.  value = cell x velocity x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
                   [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
-                  [--only batch|serving|hbtd] [--td-cap S]
+                  [--only batch|serving|hbtd|thermal_profile] [--td-cap S]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -261,6 +261,48 @@ def hb_vs_td(hb, hbcases, St, prec, cap_s, workload="shear", drop=7.0, hb_sample
     return out
 
 
+def thermal_profile(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=400.0):
+    """The paper's thermally driven cavity (Sec. 3.2, N_H = 2) converged with
+    HB-UGKS in FP64, then T/T0 along the vertical centreline x = L/2 at the
+    phases omega t = 0, pi/2, pi, 3 pi/2, rebuilt from the Fourier coefficients
+    of Eq. (40): T(t) = T_0 + 2 Re sum_k That_k exp(i k omega t).  The paper
+    quotes the gas next to the top wall at about 1.17 T0 (t = 0) and 0.79 T0
+    (t = T/2) for Kn = 0.1, St = 2, against the wall's 1.3 T0 and 0.7 T0."""
+    import numpy as np
+    case = hbcases.thermal_paper(St, Kn=Kn)
+    s = hb.Solver(case)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        s.step(1000)
+        k += 1000
+        r = s.residual()[0]
+        t = time.perf_counter() - t0
+        if k % 10000 == 0:
+            log(f"thermal profile: step {k} R_rho {r:.3e} {t:.1f} s")
+        if r <= tol or t > cap_s:
+            break
+    re, im = s.harmonics(1 << 3)  # T/T0, [1][k][cell]
+    s.close()
+    q = re[0] + 1j * im[0]  # [k][cell]
+    nx, ny = case.nx, case.ny
+    cols = [nx // 2 - 1, nx // 2] if nx % 2 == 0 else [nx // 2]
+    yc = 0.5 * (np.array(case.y_faces[:-1]) + np.array(case.y_faces[1:]))
+    prof = {}
+    for name, ph in (("0", 0.0), ("T/4", 0.5 * np.pi), ("T/2", np.pi), ("3T/4", 1.5 * np.pi)):
+        T = np.zeros(ny)
+        for i in cols:
+            cells = np.arange(ny) * nx + i
+            T += q[0, cells].real + 2.0 * np.real(
+                sum(q[kk, cells] * np.exp(1j * kk * ph) for kk in range(1, case.NH + 1)))
+        prof[name] = (T / len(cols)).tolist()
+    out = {"workload": case.name, "steps": k, "residual": r, "wall_s": t, "y": yc.tolist(), "T_centreline": prof,
+           "T_top_cell": {p_: v[-1] for p_, v in prof.items()}, "T_bottom_cell": {p_: v[0] for p_, v in prof.items()},
+           "paper_top_gas": {"0": 1.17, "T/2": 0.79}}
+    log(f"thermal profile: top cell T/T0 {out['T_top_cell']}, bottom cell {out['T_bottom_cell']}")
+    return out
+
+
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -295,7 +337,7 @@ def main():
     ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
                     help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving", "hbtd"), default=None,
+    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile"), default=None,
                     help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
                          "comparison (prints its JSON)")
     ap.add_argument("--td-cap", type=float, default=600.0,
@@ -336,6 +378,9 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
+    if args.only == "thermal_profile":
+        print(json.dumps(thermal_profile(hb, hbcases, St=args.st if args.st != 1.0 else 2.0)), flush=True)
+        return
     if args.only == "hbtd":
         prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
         print(json.dumps(hb_vs_td(hb, hbcases, args.st, prec, args.td_cap, args.workload)), flush=True)
