@@ -8,7 +8,7 @@ HBM.  value = cell x velocity x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
                   [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
-                  [--only batch|serving|hbtd|thermal_profile] [--td-cap S]
+                  [--only batch|serving|hbtd|thermal_profile|harmonic_independence] [--td-cap S]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -303,6 +303,44 @@ def thermal_profile(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=400.0):
     return out
 
 
+def harmonic_independence(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=300.0):
+    """The paper's shear cavity (Sec. 3.1) converged with N_H = 1 and N_H = 2:
+    the fundamental U_1 / U_a along the vertical centreline x = L/2 from both.
+    The paper finds the two indistinguishable at Kn = 0.1, St = 2, which is
+    why it uses N_H = 1 for the weakly forced shear cases."""
+    import numpy as np
+    out = {"St": St, "Kn": Kn, "runs": {}}
+    prof = {}
+    for NH in (1, 2):
+        case = hbcases.shear_paper(St, Kn=Kn, NH=NH)
+        s = hb.Solver(case)
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            s.step(1000)
+            k += 1000
+            r = s.residual()[0]
+            t = time.perf_counter() - t0
+            if r <= tol or t > cap_s:
+                break
+        re, im = s.harmonics(1 << 1)  # U, [1][k][cell]
+        s.close()
+        nx, ny = case.nx, case.ny
+        cols = [nx // 2 - 1, nx // 2]
+        u1 = sum(re[0, 1, np.arange(ny) * nx + i] + 1j * im[0, 1, np.arange(ny) * nx + i] for i in cols) / 2
+        prof[NH] = 2.0 * u1 / case.walls[2][1]  # amplitude 2 qhat_1 over U_a
+        out["runs"][f"NH{NH}"] = {"steps": k, "residual": r, "wall_s": t}
+        log(f"harmonic independence: N_H = {NH}, {k} steps, R_rho {r:.2e}, {t:.1f} s")
+    d = np.abs(prof[2] - prof[1])
+    out["max_abs_diff"] = float(np.max(d))
+    out["max_rel_diff"] = float(np.max(d) / np.max(np.abs(prof[1])))
+    out["U1_centreline_NH1"] = {"re": prof[1].real.tolist(), "im": prof[1].imag.tolist()}
+    out["U1_centreline_NH2"] = {"re": prof[2].real.tolist(), "im": prof[2].imag.tolist()}
+    log(f"harmonic independence: max |U1(N_H=2) - U1(N_H=1)| / U_a = {out['max_abs_diff']:.2e} "
+        f"({out['max_rel_diff']:.2e} of the largest)")
+    return out
+
+
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -337,7 +375,8 @@ def main():
     ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
                     help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile"), default=None,
+    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile", "harmonic_independence"),
+                    default=None,
                     help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
                          "comparison (prints its JSON)")
     ap.add_argument("--td-cap", type=float, default=600.0,
@@ -378,6 +417,9 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
+    if args.only == "harmonic_independence":
+        print(json.dumps(harmonic_independence(hb, hbcases)), flush=True)
+        return
     if args.only == "thermal_profile":
         print(json.dumps(thermal_profile(hb, hbcases, St=args.st if args.st != 1.0 else 2.0)), flush=True)
         return
