@@ -24,3 +24,23 @@ def test_paper_cases():
     t = hbcases.thermal_paper(2.0)
     assert (t.nx, t.ny, t.NH) == (90, 90, 2) and t.walls[2][3:] == (1.0, 0.3, 0.0)
     assert all(w[:3] == (0.0, 0.0, 0.0) for w in t.walls)
+
+
+def test_time_domain_step_size():
+    """The time-domain comparison step: CFL 0.5 of Eqs. (31)-(32) on the
+    smallest cell at the hottest wall temperature, a whole number of steps per
+    forcing period."""
+    import bench
+    import paper_2605_03479_amd as hb
+    from paper_2605_03479_amd import build as hb_build
+    if hb_build.stale():
+        hb_build.build()
+    for case in (hbcases.shear_paper(30.0), hbcases.thermal_paper(2.0)):
+        dt, ns = bench.td_step_size(hb, case)
+        assert abs(ns * dt - 2.0 * np.pi / case.St) <= 1e-12
+        u, _ = hb.hb_vgrid_nodes(case.M, case.umax, case.vrule)
+        tmax = max(w[3] + np.hypot(w[4], w[5]) for w in case.walls)
+        ut = u[-1] + np.sqrt((case.K + 4.0) / (case.K + 2.0) * tmax / 2.0)
+        nu = 2.0 * ut / np.min(np.diff(case.x_faces))
+        assert nu * dt <= case.cfl * (1.0 + 1e-12)
+        assert nu * 2.0 * np.pi / case.St / (ns - 1) > case.cfl  # one step fewer would break the bound
