@@ -8,7 +8,7 @@ HBM.  value = cell x velocity x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
                   [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
-                  [--only batch|serving|hbtd|thermal_profile|harmonic_independence] [--td-cap S]
+                  [--only batch|serving|hbtd|thermal_profile|harmonic_independence|thermal_harmonics] [--td-cap S]
 Besides the headline (FP64), the JSON line carries secondary measurements:
 the same case in the mixed form (FP32 storage of the deviation from the rest
 Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
@@ -341,6 +341,44 @@ def harmonic_independence(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=300.0):
     return out
 
 
+def thermal_harmonics(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=280.0):
+    """The paper's thermal cavity (Sec. 3.2) converged with N_H = 1, 2, 3: the
+    vertical velocity V over the cavity at t = T/2, rebuilt from the Fourier
+    coefficients of Eq. (40).  The paper finds N_H = 1 under-predicting the
+    peak response and N_H = 2, 3 virtually identical."""
+    import numpy as np
+    out = {"St": St, "Kn": Kn, "runs": {}}
+    fields = {}
+    for NH in (1, 2, 3):
+        case = hbcases.thermal_paper(St, Kn=Kn, NH=NH)
+        s = hb.Solver(case)
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            s.step(1000)
+            k += 1000
+            r = s.residual()[0]
+            t = time.perf_counter() - t0
+            if k % 20000 == 0:
+                log(f"thermal harmonics: N_H = {NH}, step {k}, R_rho {r:.2e}, {t:.1f} s")
+            if r <= tol or t > cap_s:
+                break
+        re, im = s.harmonics(1 << 2)  # V, [1][k][cell]
+        s.close()
+        q = re[0] + 1j * im[0]
+        V = q[0].real + 2.0 * np.real(sum(q[kk] * np.exp(1j * kk * np.pi) for kk in range(1, NH + 1)))
+        fields[NH] = V
+        out["runs"][f"NH{NH}"] = {"steps": k, "residual": r, "wall_s": t, "max_abs_V_half_period": float(np.max(np.abs(V))),
+                                   "min_V": float(V.min()), "max_V": float(V.max())}
+        log(f"thermal harmonics: N_H = {NH}: {k} steps, R_rho {r:.2e}, max |V(T/2)| {np.max(np.abs(V)):.4e}")
+    ref = np.max(np.abs(fields[3]))
+    out["max_diff_NH1_vs_NH3"] = float(np.max(np.abs(fields[1] - fields[3])) / ref)
+    out["max_diff_NH2_vs_NH3"] = float(np.max(np.abs(fields[2] - fields[3])) / ref)
+    log(f"thermal harmonics: max |V1 - V3| / max |V3| = {out['max_diff_NH1_vs_NH3']:.3e}, "
+        f"max |V2 - V3| / max |V3| = {out['max_diff_NH2_vs_NH3']:.3e}")
+    return out
+
+
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -375,7 +413,8 @@ def main():
     ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
                     help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile", "harmonic_independence"),
+    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile", "harmonic_independence",
+                                       "thermal_harmonics"),
                     default=None,
                     help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
                          "comparison (prints its JSON)")
@@ -417,6 +456,9 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
+    if args.only == "thermal_harmonics":
+        print(json.dumps(thermal_harmonics(hb, hbcases)), flush=True)
+        return
     if args.only == "harmonic_independence":
         print(json.dumps(harmonic_independence(hb, hbcases)), flush=True)
         return
