@@ -516,6 +516,33 @@ def main():
                "sample": f"{steps} pseudo steps of the same 64x64x32^2 NH=1 case ({dt:.1f} s)"}
         log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads")
 
+    # time to converge: the same case from rest to R_rho <= 1e-8 (Eq. 43), residual read every 100 steps
+    conv = None
+    if not args.no_extra:
+        s = hb.Solver(case, device=0, stream=stream, precision=prec)
+        t0 = time.perf_counter()
+        k = 0
+        r = float("inf")
+        while k < 200000 and time.perf_counter() - t0 < 60.0:
+            s.step(100)
+            k += 100
+            try:
+                r = s.residual()[0]
+            except hb.HBError:
+                r = float("nan")
+                break
+            if r <= 1e-8:
+                break
+        tconv = time.perf_counter() - t0
+        s.close()
+        conv = {"tol": 1e-8, "steps": k, "residual": r, "converged": bool(r <= 1e-8), "wall_s": tconv,
+                "cases_per_h": 3600.0 / tconv}
+        if cpu is not None:
+            cpu_step = case.updates / cpu["value"]
+            conv["cpu_oracle_wall_s_extrapolated"] = k * cpu_step
+            conv["cpu_oracle_cases_per_h_extrapolated"] = 3600.0 / (k * cpu_step)
+        log(f"converge: {k} steps to R_rho {r:.2e} in {tconv:.2f} s ({conv['cases_per_h']:.0f} cases/h)")
+
     extra = []
     if not args.no_extra:
         others = []
@@ -552,6 +579,7 @@ def main():
         "kernel_avg_us": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "converge": conv,
         "other_workloads": extra,
         "batched": batched,
         "serving": serving_res,
