@@ -516,6 +516,23 @@ def main():
                "sample": f"{steps} pseudo steps of the same 64x64x32^2 NH=1 case ({dt:.1f} s)"}
         log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads")
 
+    # the oracle on one host thread, in a child process (OpenMP reads its thread count at start-up)
+    cpu1 = None
+    if cpu is not None and not args.no_extra:
+        import subprocess
+        code = ("import sys, time; sys.path.insert(0, %r); import hbcases, oracle; "
+                "c = hbcases.shear_cavity(%r, %r); o = oracle.Oracle(c); o.step(1); t = time.perf_counter(); "
+                "o.step(5); print(c.updates * 5 / (time.perf_counter() - t), oracle.threads())") % (ROOT, args.kn, args.st)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        try:
+            r1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+            v1, th1 = r1.stdout.split()[-2:]
+            cpu1 = {"value": float(v1), "unit": "updates/s", "cores": int(th1), "kind": "oracle",
+                    "sample": "5 pseudo steps of the same case"}
+            log(f"cpu oracle, one thread: {cpu1['value']:.4e} updates/s")
+        except Exception as e:  # the baseline is context; the GPU numbers stand without it
+            log(f"cpu oracle, one thread: not measured ({e})")
+
     # time to converge: the same case from rest to R_rho <= 1e-8 (Eq. 43), residual read every 100 steps
     conv = None
     if not args.no_extra:
@@ -563,6 +580,17 @@ def main():
                           "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
 
+    # per-step time over the shear cases' Kn x St grid (the arithmetic per step does not depend on them)
+    knst = None
+    if not args.no_extra and args.workload == "shear":
+        knst = []
+        for kn in hbcases.SHEAR_KN:
+            for st in hbcases.SHEAR_ST:
+                c3 = hbcases.shear_cavity(kn, st)
+                ms3, _, _ = timed_run(hb, c3, prec, stream, sync, 30, 5)
+                knst.append({"Kn": kn, "St": st, "ms_per_step": ms3, "updates_per_s": c3.updates / (ms3 * 1e-3)})
+        log("Kn x St sweep: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst))
+
     batched = serving_res = None
     if not args.no_extra:
         batched = batched_sweep(hb, hbcases)
@@ -579,7 +607,9 @@ def main():
         "kernel_avg_us": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
         "converge": conv,
+        "kn_st_sweep": knst,
         "other_workloads": extra,
         "batched": batched,
         "serving": serving_res,
