@@ -32,6 +32,9 @@ CASES = [
     (Case(16, 16, 20, 4.0, 0.05, 0.5, 3, hbcases.lid_walls(0.02)), 0),
     (Case(10, 8, 16, 4.0, 5.0, 8.0, 1, hbcases.lid_walls(0.01)), 1),
     (Case(7, 7, 24, 5.0, 1.0, 1.0, 4, hbcases.thermal_walls(0.2, 2, "cos")), 1),
+    # Gauss-Hermite velocities on a wall-refined mesh
+    (Case(10, 9, 14, 0.0, 0.1, 3.0, 1, hbcases.lid_walls(0.01), x_faces=hbcases.stretched_faces(10, 1.0, 0.02),
+          y_faces=hbcases.stretched_faces(9, 1.0, 0.02), vrule=1), 0),
 ]
 
 
