@@ -263,7 +263,7 @@ static int build_lists(hb_batch *B)
         const double cc = (double)P.nvp * P.NT;
         cg.mom_nvp[pm] = std::max(cg.mom_nvp[pm], P.nvp);
         for (int c = 0; c < P.nc; c++) {
-            cg.mom[pm].items.push_back({s, c});
+            cg.mom[pm].items.push_back({s, hb::strip_cell(c, P.nx, P.ny)});
             cg.mom[pm].cost.push_back(cc);
         }
         const int nf = ((P.nx + 1) * P.ny + P.nx * (P.ny + 1)) * P.NT;
@@ -292,7 +292,7 @@ static int build_lists(hb_batch *B)
         g.max_nvp = std::max(g.max_nvp, P.nvp);
         g.lds = std::max(g.lds, H->upd_lds);
         for (int ci = 0; ci < H->n_int; ci++) {
-            g.in.items.push_back({s, ci});
+            g.in.items.push_back({s, hb::strip_cell(ci, P.nx - 4, P.ny - 4)});
             g.in.cost.push_back(cc);
         }
         for (int c : H->bnd_host) {

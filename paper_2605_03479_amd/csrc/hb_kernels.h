@@ -25,6 +25,27 @@ __device__ inline int xcd_cell(int b, int G)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Position p of a walk over an nx x ny grid in eight column strips (the
+// first nx % 8 strips one column wider), each strip row by row -> row-major
+// cell index.  Composed with xcd_cell, each XCD walks one strip down the
+// grid, so the vertical stencil neighbours of a cell are revisited while they
+// are still in that XCD's L2; in row-major order they are a whole row of
+// cells apart.  The batched work lists use the same order.
+__host__ __device__ inline int strip_cell(int p, int nx, int ny)
+{
+    const int q = nx >> 3, rem = nx & 7;
+    const int big = rem * (q + 1) * ny;
+    int w, c0, r;
+    if (p < big) {
+        const int s = p / ((q + 1) * ny);
+        w = q + 1, c0 = s * (q + 1), r = p - s * (q + 1) * ny;
+    } else {  // only reached when q > 0
+        const int pp = p - big, s = pp / (q * ny);
+        w = q, c0 = rem * (q + 1) + s * q, r = pp - s * q * ny;
+    }
+    return (r / w) * nx + c0 + r % w;
+}
+
 // Storage of (h, b): FP64 values, or FP32 deviations from the rest Maxwellian
 // H_ref = exp(-|u|^2)/pi (B_ref = K/2 H_ref) for the mixed form.  All
 // arithmetic below runs in FP64 either way.
@@ -255,7 +276,7 @@ template <typename TS>
 __global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                  double *__restrict__ feed)
 {
-    moments_cell<TS>(P, h, b, feed, xcd_cell(blockIdx.x, gridDim.x));
+    moments_cell<TS>(P, h, b, feed, strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx, P.ny));
 }
 
 // ---------------------------------------------------------------- K2: faces
@@ -710,12 +731,6 @@ __device__ inline void resid_block(const double *__restrict__ rpart, int nblk, i
     }
 }
 
-__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
-                                               int slot, int *__restrict__ flag)
-{
-    resid_block(rpart, nblk, nc, ring, slot, flag);
-}
-
 // Period residual of the time-domain solver, Eq. (43) second line: RMS over
 // cells of W(nT) - W((n-1)T) for one level (W[c][4]); one block, fixed-order sums.
 __global__ __launch_bounds__(256) void k_period_diff(const double *__restrict__ Wa, const double *__restrict__ Wb,
@@ -1017,7 +1032,8 @@ __global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, con
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
                                                        TS *__restrict__ bn)
 {
-    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, xcd_cell(blockIdx.x, gridDim.x));
+    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn,
+                            strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx - 4, P.ny - 4));
 }
 
 // Cells within two of a wall (listed in cells[]): the general stencil with
