@@ -580,7 +580,8 @@ def main():
                           "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
 
-    # per-step time over the shear cases' Kn x St grid (the arithmetic per step does not depend on them)
+    # per-step time over the Kn x St grids of the shear and thermal cases (the arithmetic per step does not
+    # depend on them)
     knst = None
     if not args.no_extra and args.workload == "shear":
         knst = []
@@ -588,8 +589,17 @@ def main():
             for st in hbcases.SHEAR_ST:
                 c3 = hbcases.shear_cavity(kn, st)
                 ms3, _, _ = timed_run(hb, c3, prec, stream, sync, 30, 5)
-                knst.append({"Kn": kn, "St": st, "ms_per_step": ms3, "updates_per_s": c3.updates / (ms3 * 1e-3)})
+                knst.append({"workload": c3.name, "precision": args.precision, "Kn": kn, "St": st, "ms_per_step": ms3,
+                             "updates_per_s": c3.updates / (ms3 * 1e-3)})
         log("Kn x St sweep: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst))
+        # and over the thermal cases' grid, in the mixed form those cases are defined in
+        for kn in hbcases.THERMAL_KN:
+            for st in hbcases.THERMAL_ST:
+                c3 = hbcases.thermal_cavity(kn, st)
+                ms3, _, _ = timed_run(hb, c3, hb.HB_MIXED, stream, sync, 20, 5)
+                knst.append({"workload": c3.name, "precision": "mixed", "Kn": kn, "St": st, "ms_per_step": ms3,
+                             "updates_per_s": c3.updates / (ms3 * 1e-3)})
+        log("thermal Kn x St: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst[-4:]))
 
     batched = serving_res = None
     if not args.no_extra:

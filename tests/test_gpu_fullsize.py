@@ -9,7 +9,11 @@
   size: a resting Maxwellian between walls at rest stays at rest, and a
   bottom wall heated uniformly keeps the solution mirror-symmetric in x.
 - The largest velocity grid with the most levels (128^2, N_T = 11) needs
-  180 KB of tables per block, more than a CU's LDS: set-up refuses it."""
+  180 KB of tables per block, more than a CU's LDS: set-up refuses it.
+- The 64-case seeded sweep as one tuned mixed batch (40 GB of state, the
+  benchmark's launch shapes): sampled cases, the smallest, the largest and
+  two seeded others, are bit-identical to the same case stepped alone, and
+  the smallest one matches the oracle to the mixed bound."""
 import numpy as np
 import pytest
 
@@ -95,3 +99,36 @@ def test_largest_tables_refused(gpu):
     with pytest.raises(gpu.HBError) as e:
         gpu.Solver(Case(8, 8, 128, 5.0, 1.0, 1.0, 5, hbcases.lid_walls(0.01)))
     assert e.value.code == gpu.HB_EINVAL
+
+
+def test_full_sweep_sampled_cases(gpu, oracle_mod):
+    cases = hbcases.batch_sweep()
+    steps = 2
+    B = gpu.Batch(max_cases=len(cases))
+    hs = [B.add(c, gpu.HB_MIXED) for c in cases]
+    B.tune(2)  # takes one batch step
+    B.step(steps)
+    res = B.residuals()
+    assert all(res[h.cid][1] == steps + 1 and not res[h.cid][2] for h in hs)
+    order = sorted(range(len(cases)), key=lambda k: cases[k].updates)
+    rng = np.random.Generator(np.random.PCG64(2605))
+    pick = [order[0], order[-1]] + [int(k) for k in rng.choice(order[1:-1], 2, replace=False)]
+    for k in pick:
+        c = cases[k]
+        _say(f"  {c.name}: {c.nx}x{c.ny}, M={c.M}, NH={c.NH}, {c.updates:.3g} updates/step")
+        s = gpu.Solver(c, precision=gpu.HB_MIXED)
+        s.step(steps + 1)
+        solo = s.state()
+        assert all(np.array_equal(x, y) for x, y in zip(hs[k].state(), solo)), c.name
+        assert np.array_equal(res[hs[k].cid][0], s.residual()), c.name
+        if k == order[0]:
+            o = oracle_mod.Oracle(c)
+            rest = [x.copy() for x in o.state()]
+            o.step(steps + 1)
+            for name, a, r, r0 in zip("Whb", solo, o.state(), rest):
+                err = _rel(a, r, r0)
+                _say(f"    {name} against the oracle: rel err {err:.3e}")
+                assert err <= 1e-6, (name, err)
+        s.close()
+        del solo
+    B.close()
