@@ -373,6 +373,22 @@ __device__ inline void store_side(double *rec, int side, double lam, double Un, 
 }
 
 // one (face, level) per thread t; x-faces first, then y-faces
+// Face slot -> face index (x-faces row by row, then y-faces).  The slots list
+// the interior faces first (x, then y) and the wall faces last, so that a
+// wave runs either the interior or the wall branch of the face kernel, not
+// both one after the other.
+__device__ inline int face_of_slot(int s, int nx, int ny)
+{
+    const int nfx = (nx + 1) * ny, ix = (nx - 1) * ny, iy = nx * (ny - 1);
+    if (s < ix) return (s / (nx - 1)) * (nx + 1) + 1 + s % (nx - 1);
+    s -= ix;
+    if (s < iy) return nfx + nx + s;
+    s -= iy;
+    if (s < 2 * ny) return (s >> 1) * (nx + 1) + ((s & 1) ? nx : 0);
+    s -= 2 * ny;
+    return nfx + (s < nx ? s : ny * nx + s - nx);
+}
+
 __device__ inline void faces_thread(const Params &P, const double *__restrict__ feed, const double *__restrict__ W,
                                     const double *__restrict__ dtc, double *__restrict__ recx,
                                     double *__restrict__ recy, int t)
@@ -381,7 +397,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
     const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
     if (t >= (nfx + nfy) * NT) return;
     const int n = t % NT;
-    int f = t / NT;
+    int f = face_of_slot(t / NT, nx, ny);
     bool isx = f < nfx;
     int cL, cR, lo_end;  // cells on the low/high side (-1 if wall)
     double xL = 0, xF = 0, xR = 0;
