@@ -240,19 +240,25 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
                 if (k < kn) rb[k * K1_ROW + lane] = acc[k0 + k];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (lane < kn) {
-                const double2 *row = reinterpret_cast<const double2 *>(rb + lane * K1_ROW);
+            // row k is summed by two lanes, k over its first 32 entries and
+            // k + 32 over the last 32; lane k then adds its partner's part
+            const int rk = lane & 31;
+            double part = 0.0;
+            if (rk < kn) {
+                const double2 *row = reinterpret_cast<const double2 *>(rb + rk * K1_ROW + (lane & 32));
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-                for (int l = 0; l < 32; l += 2) {
+                for (int l = 0; l < 16; l += 2) {
                     const double2 x0 = row[l], x1 = row[l + 1];
                     s0 += x0.x;
                     s1 += x0.y;
                     s2 += x1.x;
                     s3 += x1.y;
                 }
-                wsum[q][k0 + lane] = (s0 + s1) + (s2 + s3);
+                part = (s0 + s1) + (s2 + s3);
             }
+            const double other = __shfl_down(part, 32);
+            if (lane < kn) wsum[q][k0 + lane] = part + other;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
