@@ -428,13 +428,9 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         lo_end = fj == 0;
         rec = recy + ((long)f * NT + n) * REC;
     }
-    // global -> face-frame index maps (y-faces: n = v, t = u)
-    const int p10x[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9}, p10y[10] = {0, 2, 1, 5, 4, 3, 9, 8, 7, 6};
-    const int p3x[3] = {0, 1, 2}, p3y[3] = {0, 2, 1};
-    const int p4x[4] = {0, 1, 2, 3}, p4y[4] = {0, 2, 1, 3};
-    const int *p10 = isx ? p10x : p10y;
-    const int *p3i = isx ? p3x : p3y;
-    const int *p4 = isx ? p4x : p4y;
+    // global -> face-frame index maps (y-faces: n = v, t = u), applied with
+    // compile-time indices so that no array is indexed at run time
+    constexpr int p10y[10] = {0, 2, 1, 5, 4, 3, 9, 8, 7, 6}, p3y[3] = {0, 2, 1}, p4y[4] = {0, 2, 1, 3};
     // feeds: low cell feeds through its high face (E or N), high cell through its low face (W or S)
     const int offHi = isx ? FEED_E : FEED_N, offLo = isx ? FEED_W : FEED_S;
     double m[10], mb[3], ts[4], c5s[4];
@@ -442,11 +438,16 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         const double *fa = cL >= 0 ? feed + ((long)cL * NT + n) * FEED + offHi : nullptr;
         const double *fb = cR >= 0 ? feed + ((long)cR * NT + n) * FEED + offLo : nullptr;
         double g[21];
+#pragma unroll
         for (int k = 0; k < 21; k++) g[k] = (fa ? fa[k] : 0.0) + (fb ? fb[k] : 0.0);
-        for (int k = 0; k < 10; k++) m[k] = g[p10[k]];
-        for (int k = 0; k < 3; k++) mb[k] = g[10 + p3i[k]];
-        for (int k = 0; k < 4; k++) ts[k] = g[13 + p4[k]];
-        for (int k = 0; k < 4; k++) c5s[k] = g[17 + p4[k]];
+#pragma unroll
+        for (int k = 0; k < 10; k++) m[k] = isx ? g[k] : g[p10y[k]];
+#pragma unroll
+        for (int k = 0; k < 3; k++) mb[k] = isx ? g[10 + k] : g[10 + p3y[k]];
+#pragma unroll
+        for (int k = 0; k < 4; k++) ts[k] = isx ? g[13 + k] : g[13 + p4y[k]];
+#pragma unroll
+        for (int k = 0; k < 4; k++) c5s[k] = isx ? g[17 + k] : g[17 + p4y[k]];
     }
     const double S4[4] = {m[1], m[3], m[4], 0.5 * (m[6] + m[8]) + 0.5 * mb[1]};
     double F[4];
@@ -464,9 +465,10 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         double WL[4], WR[4];
         {
             const double *a = W + ((long)cL * NT + n) * 4, *bb = W + ((long)cR * NT + n) * 4;
+#pragma unroll
             for (int k = 0; k < 4; k++) {
-                WL[k] = a[p4[k]];
-                WR[k] = bb[p4[k]];
+                WL[k] = a[isx ? k : p4y[k]];
+                WR[k] = bb[isx ? k : p4y[k]];
             }
         }
         double dWL[4], dWR[4], dWt[4];
