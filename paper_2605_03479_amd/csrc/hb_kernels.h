@@ -311,16 +311,32 @@ __device__ inline void face_state(int K, const double m[10], const double mb[3],
     s.qt = 0.5 * (mu21 + mu03 + mb[2] - Ut * mb[0]);
 }
 
+// Read-only data every lane of the wave reads at the same address: typed in
+// the constant address space so the loads are scalar (SMEM, into SGPRs) and
+// never wait behind the vector loads of the stencil.
+typedef __attribute__((address_space(4))) const double cdouble;
+
+template <typename Ptr>
+__device__ inline cdouble *wave_uniform(Ptr p)
+{
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    return (cdouble *)((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // 1-D sums G[k] = sum_i w_i x_i^k exp(-lam (x_i - U)^2), k = 0..6, over nodes
 // with sign selection sel (0 all, 1 x>0, 2 x<0).
 __device__ inline void gsums(const Params &P, double lam, double U, int sel, double G[7])
 {
 #pragma unroll
     for (int k = 0; k < 7; k++) G[k] = 0.0;
+    cdouble *u1 = wave_uniform(P.u1), *w1 = wave_uniform(P.w1);
+#pragma unroll 4
     for (int k = 0; k < P.M; k++) {
-        const double x = P.u1[k];
+        const double x = u1[k];
         if ((sel == 1 && !(x > 0.0)) || (sel == 2 && !(x < 0.0))) continue;
-        double t = P.w1[k] * exp(-lam * (x - U) * (x - U));
+        double t = w1[k] * exp(-lam * (x - U) * (x - U));
 #pragma unroll
         for (int p = 0; p < 7; p++) {
             G[p] += t;
@@ -337,9 +353,10 @@ __device__ inline void gsums2(const Params &P, double lam, double Un, double Ut,
 {
 #pragma unroll
     for (int k = 0; k < 7; k++) Gn[k] = Gt[k] = 0.0;
+    cdouble *u1 = wave_uniform(P.u1), *w1 = wave_uniform(P.w1);
 #pragma unroll 4
     for (int k = 0; k < P.M; k++) {
-        const double x = P.u1[k], w = P.w1[k];
+        const double x = u1[k], w = w1[k];
         double tn = w * exp(-lam * (x - Un) * (x - Un)), tt = w * exp(-lam * (x - Ut) * (x - Ut));
 #pragma unroll
         for (int p = 0; p < 7; p++) {
@@ -808,19 +825,6 @@ __device__ inline double p3_eval(Ptr c, double n, double t)
     return __builtin_fma(t, f, fma_s(n, e, c[0]));
 }
 
-// Read-only data every lane of the wave reads at the same address: typed in
-// the constant address space so the loads are scalar (SMEM, into SGPRs) and
-// never wait behind the vector loads of the stencil.
-typedef __attribute__((address_space(4))) const double cdouble;
-
-template <typename Ptr>
-__device__ inline cdouble *wave_uniform(Ptr p)
-{
-    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
-    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
-    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
-    return (cdouble *)((static_cast<unsigned long long>(hi) << 32) | lo);
-}
 
 // micro flux through one face for this lane: u_n (e Q(n,t) + c4 f0 + c5 s)
 template <typename Ptr>
