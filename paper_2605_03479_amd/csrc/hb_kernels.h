@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
                                                        TS *__restrict__ bn)
 {
-    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, cells[blockIdx.x]);
+    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, cells[xcd_cell(blockIdx.x, gridDim.x)]);
 }
 
 // ---------------------------------------------------------------- set-up kernels

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hb_handle.h"
@@ -436,10 +437,26 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
     ALLOC(H->vref, nvp, double);
+    // The boundary ring (cells within two of a wall), listed as a walk around
+    // the cavity: each cell is keyed by the perimeter position of its nearest
+    // wall, then by its depth.  Contiguous ranges of the list, one per XCD,
+    // are then stretches of the ring whose stencils overlap.
     std::vector<int> bnd;
-    for (int jj = 0; jj < ny; jj++)
-        for (int ii = 0; ii < nx; ii++)
-            if (ii < 2 || ii > nx - 3 || jj < 2 || jj > ny - 3) bnd.push_back(jj * nx + ii);
+    {
+        std::vector<std::tuple<long, int, int>> key;
+        for (int jj = 0; jj < ny; jj++)
+            for (int ii = 0; ii < nx; ii++)
+                if (ii < 2 || ii > nx - 3 || jj < 2 || jj > ny - 3) {
+                    const int d[4] = {jj, nx - 1 - ii, ny - 1 - jj, ii};
+                    const long sp[4] = {ii, (long)nx + jj, (long)nx + ny + (nx - 1 - ii), 2L * nx + ny + (ny - 1 - jj)};
+                    int w = 0;
+                    for (int k = 1; k < 4; k++)
+                        if (d[k] < d[w]) w = k;
+                    key.emplace_back(sp[w], d[w], jj * nx + ii);
+                }
+        std::sort(key.begin(), key.end());
+        for (const auto &t : key) bnd.push_back(std::get<2>(t));
+    }
     H->n_bnd = (int)bnd.size();
     H->n_int = P.nc - H->n_bnd;
     ALLOC(H->bnd_cells, bnd.size(), int);
