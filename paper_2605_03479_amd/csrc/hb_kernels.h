@@ -122,7 +122,11 @@ template <typename TS>
 __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                     double *__restrict__ feed, int c)
 {
-    __shared__ double red[4][28 * K1_ROW];
+    // LDS rows per reduction pass: 24 in the mixed form, whose kernel runs
+    // three blocks per CU (three 52 KB buffers fit the 160 KB LDS); 28 with
+    // FP64 storage, which needs the registers of two blocks per CU
+    constexpr int RPP = sizeof(TS) == 4 ? 24 : 28, NPASS = (NMOM + RPP - 1) / RPP;
+    __shared__ double red[4][RPP * K1_ROW];
     __shared__ double wsum[4][NMOM];
     const int i = c % P.nx, j = c / P.nx;
     const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -228,15 +232,16 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
             acc[53] += wm[1] * bc;
             acc[54] += wm[2] * bc;
         }
-        // wave reduction in two halves through LDS: lane k sums row k.  Each
+        // wave reduction through LDS in passes of RPP rows (row k = sum k of
+        // the 64 lanes), two lanes per row.  Each
         // wave works in its own rows, so a wave-level fence orders the writes
         // before the reads; only the quadrant combine below needs the block.
         double *rb = red[q];
 #pragma unroll
-        for (int half = 0; half < 2; half++) {
-            const int k0 = half * 28, kn = half ? NMOM - 28 : 28;
+        for (int half = 0; half < NPASS; half++) {
+            const int k0 = half * RPP, kn = NMOM - k0 < RPP ? NMOM - k0 : RPP;
 #pragma unroll
-            for (int k = 0; k < 28; k++)
+            for (int k = 0; k < RPP; k++)
                 if (k < kn) rb[k * K1_ROW + lane] = acc[k0 + k];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -278,8 +283,13 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     }
 }
 
+// Blocks per CU the moments kernel is compiled for: three in the mixed form
+// (168 VGPRs, no spills), one bound (the compiler's own, two per CU) with FP64
+// storage, where 168 VGPRs would spill.
+#define HB_MOM_MINBLK(TS) (sizeof(TS) == 4 ? 3 : 1)
+
 template <typename TS>
-__global__ __launch_bounds__(256) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+__global__ __launch_bounds__(256, HB_MOM_MINBLK(TS)) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                  double *__restrict__ feed)
 {
     moments_cell<TS>(P, h, b, feed, strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx, P.ny));
