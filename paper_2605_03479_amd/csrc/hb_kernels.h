@@ -122,10 +122,9 @@ template <typename TS>
 __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                     double *__restrict__ feed, int c)
 {
-    // LDS rows per reduction pass: 24 in the mixed form, whose kernel runs
-    // three blocks per CU (three 52 KB buffers fit the 160 KB LDS); 28 with
-    // FP64 storage, which needs the registers of two blocks per CU
-    constexpr int RPP = sizeof(TS) == 4 ? 24 : 28, NPASS = (NMOM + RPP - 1) / RPP;
+    // LDS rows per reduction pass: 24, so that three blocks' 52 KB buffers
+    // fit a CU's 160 KB of LDS
+    constexpr int RPP = 24, NPASS = (NMOM + RPP - 1) / RPP;
     __shared__ double red[4][RPP * K1_ROW];
     __shared__ double wsum[4][NMOM];
     const int i = c % P.nx, j = c / P.nx;
@@ -166,26 +165,16 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
         d.bN = ldv<TS>(bp, oN, rb);
         return d;
     };
-    // (level, row) pairs in order.  With FP64 storage the loads of the next
-    // pair are issued before the arithmetic (and the level's reduction) of the
-    // current one; the mixed form measured no gain from it, so it loads in place.
-    constexpr bool PIPE = sizeof(TS) == 8;
+    // Loads in place: the kernel runs three blocks per CU (three waves per
+    // SIMD), which hides their latency better than loading the next (level,
+    // row) pair ahead, whose registers cost the third block.
     const int nch = P.Qp / 64;
-    Ld nxt{};
-    if constexpr (PIPE) nxt = load(0, lane);
     for (int n = 0; n < NT; n++) {
         double acc[NMOM];
 #pragma unroll
         for (int k = 0; k < NMOM; k++) acc[k] = 0.0;
         for (int ch = 0; ch < nch; ch++) {
-            Ld d;
-            if constexpr (PIPE) {
-                d = nxt;
-                const int nn = ch + 1 < nch ? n : n + 1, rr = ch + 1 < nch ? lane + 64 * (ch + 1) : lane;
-                if (nn < NT) nxt = load(nn, rr);
-            } else {
-                d = load(n, lane + 64 * ch);
-            }
+            const Ld d = load(n, lane + 64 * ch);
             const double u = d.u, v = d.v, w = d.w;
             const double hc = d.hc, bc = d.bc;
             const double sxh = slope_c(d.hW, hc, d.hE, mx, rxm, rxp), sxb = slope_c(d.bW, bc, d.bE, mx, rxm, rxp);
@@ -283,13 +272,12 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     }
 }
 
-// Blocks per CU the moments kernel is compiled for: three in the mixed form
-// (168 VGPRs, no spills), one bound (the compiler's own, two per CU) with FP64
-// storage, where 168 VGPRs would spill.
-#define HB_MOM_MINBLK(TS) (sizeof(TS) == 4 ? 3 : 1)
+// Blocks per CU the moments kernel is compiled for: three (168 VGPRs, three
+// waves per SIMD).
+#define HB_MOM_MINBLK 3
 
 template <typename TS>
-__global__ __launch_bounds__(256, HB_MOM_MINBLK(TS)) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+__global__ __launch_bounds__(256, HB_MOM_MINBLK) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                  double *__restrict__ feed)
 {
     moments_cell<TS>(P, h, b, feed, strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx, P.ny));
