@@ -424,7 +424,7 @@ def main():
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(batched cases would shard by case with no communication).", file=sys.stderr)
         sys.exit(2)
 
