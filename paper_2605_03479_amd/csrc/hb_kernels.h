@@ -1152,7 +1152,11 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
         };
         Lv nxt{};
         if constexpr (PIPE) nxt = ld_level(0);
-#pragma unroll 1
+        // the level loop unrolled up to three levels (the compiler can then
+        // interleave one level's record loads and tables with the previous
+        // level's arithmetic), kept rolled above for code size
+        constexpr int UNR = NT <= 3 ? NT : 1;
+#pragma unroll UNR
         for (int n = 0; n < NT; n++) {
             double hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
             if constexpr (PIPE) {
