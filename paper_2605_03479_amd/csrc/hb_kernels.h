@@ -712,11 +712,20 @@ __device__ inline void cells_block(const Params &P, const double *__restrict__ f
         const double *Fs = recy + ((long)(j * nx + i) * NT + n) * REC;
         const double *Fn = recy + ((long)((j + 1) * nx + i) * NT + n) * REC;
         double Wnew[4];
+        // spectral source sum_m E_nm W_m, each sum in level order.  The loop
+        // runs to the largest level count so that all its loads issue at once;
+        // indices past NT are clamped and their terms weighted by zero.
+        double src[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mm = 0; mm < HB_NTMAX; mm++) {
+            const int m2 = mm < NT ? mm : NT - 1;
+            const double e = P.E[n * NT + m2] * (mm < NT ? 1.0 : 0.0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) src[k] += e * Wc[m2 * 4 + k];
+        }
         for (int k = 0; k < 4; k++) {
-            double src = 0.0;
-            for (int mm = 0; mm < NT; mm++) src += P.E[n * NT + mm] * Wc[mm * 4 + k];
             const double div = (Fe[k] - Fw[k]) * P.rdx[i] + (Fn[k] - Fs[k]) * P.rdy[j];
-            Wnew[k] = Wc[n * 4 + k] - dG * (div + P.omega * src);
+            Wnew[k] = Wc[n * 4 + k] - dG * (div + P.omega * src[k]);
             Wo[k] = Wnew[k];
         }
         const double *cm = feed + ((long)c * NT + n) * FEED + FEED_CM;
