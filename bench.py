@@ -30,14 +30,14 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "32503f9ea958a58b",
+    "sources_sha256_16": "47314b697498c922",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 263777960,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 626240954,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73638451,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1175575528,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2860544351,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 452543617,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 263843921,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 627508200,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73647365,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1175654889,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2877582818,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 452747898,
     },
 }
 
