@@ -30,7 +30,7 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "47314b697498c922",
+    "sources_sha256_16": "01c235d4cb5149e4",
     "bytes": {
         "shear64_v32_nh1_kn1_st1/fp64/moments": 263843921,
         "shear64_v32_nh1_kn1_st1/fp64/update_int": 627508200,

@@ -272,12 +272,14 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     }
 }
 
-// Blocks per CU the moments kernel is compiled for: three (168 VGPRs, three
-// waves per SIMD).
-#define HB_MOM_MINBLK 3
+// Second __launch_bounds__ argument: hipcc reads it as the minimum number of
+// waves per SIMD the kernel must fit, which sets its VGPR budget (512 / waves).
+// The moments kernel: three waves per SIMD, 168 VGPRs (three 256-thread
+// blocks per CU).
+#define HB_MOM_WAVES 3
 
 template <typename TS>
-__global__ __launch_bounds__(256, HB_MOM_MINBLK) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+__global__ __launch_bounds__(256, HB_MOM_WAVES) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                  double *__restrict__ feed)
 {
     moments_cell<TS>(P, h, b, feed, strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx, P.ny));
@@ -908,9 +910,9 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
 
 // Interior cells (2 <= i <= nx-3, 2 <= j <= ny-3): every stencil value exists
 // and every slope is limited, so the per-velocity work is straight-line code.
-#ifndef HB_UPD_MINBLK
-#define HB_UPD_MINBLK 2
-#endif
+// Minimum waves per SIMD of the interior update (see HB_MOM_WAVES): two, so
+// up to 256 VGPRs; at three levels the body needs 120 and runs at four.
+#define HB_UPD_WAVES 2
 template <int NT, typename TS>
 __device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
@@ -1060,7 +1062,7 @@ __device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h
 }
 
 template <int NT, typename TS>
-__global__ __launch_bounds__(256, HB_UPD_MINBLK) void k_update_int(Params P, const TS *__restrict__ h,
+__global__ __launch_bounds__(256, HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
                                                        const TS *__restrict__ b, const double *__restrict__ recx,
                                                        const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
