@@ -35,6 +35,9 @@ MEASURED_TRAFFIC = {
         "shear64_v32_nh1_kn1_st1/fp64/moments": 263843921,
         "shear64_v32_nh1_kn1_st1/fp64/update_int": 627508200,
         "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73647365,
+        "shear64_v32_nh1_kn1_st1/mixed/moments": 143719223,
+        "shear64_v32_nh1_kn1_st1/mixed/update_int": 307585339,
+        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38170065,
         "thermal64_v48_nh4_kn1_st1/mixed/moments": 1175654889,
         "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2877582818,
         "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 452747898,
