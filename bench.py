@@ -1,18 +1,22 @@
 """Benchmark: HB-UGKS pseudo steps per second on one MI355X.
 
 One step = one pass of the whole pseudo step (moments, faces, cells,
-residual, update) over the 64 x 64-cell, 32 x 32-velocity, NH = 1 shear
-cavity (Kn = 1, St = 1, lid 0.01 cos wt, Shakhov), FP64, state resident in
-HBM.  value = cell x velocity x level updates per second.
+local steps + residual, interior and boundary-ring update) over the
+64 x 64-cell, 48 x 48-velocity (on [-5, 5]), N_H = 4 (nine levels) thermal
+cavity (Kn = 1, St = 1, bottom wall T0 (1 + 0.5 sin wt), Shakhov) in the
+mixed form (FP32 storage of the deviation from the rest Maxwellian, FP64
+moments, W and residual), state resident in HBM.  value = cell x velocity
+x level updates per second.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--cpu-steps S]
-                  [--precision fp64|mixed] [--workload shear|thermal] [--no-extra] [--copy-mib N]
-                  [--only batch|serving|hbtd|thermal_profile|harmonic_independence|thermal_harmonics] [--td-cap S]
-Besides the headline (FP64), the JSON line carries secondary measurements:
-the same case in the mixed form (FP32 storage of the deviation from the rest
-Maxwellian, FP64 arithmetic) and the 64 x 64-cell, 48 x 48-velocity, NH = 4
-thermal cavity in the mixed form.
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                  [--precision fp64|mixed] [--workload thermal|shear] [--no-extra] [--copy-mib N]
+                  [--only batch|serving|hbtd] [--td-cap S]
+Besides the headline, the JSON line carries: the headline case's one-step
+error against the FP64 oracle at full size, the oracle timed on the host
+(all threads and one), the time to converge from rest, the 64 x 64-cell,
+32 x 32-velocity, N_H = 1 shear cavity in both forms, per-step times over
+the Kn x St grids, and the 64-case batched sweep.
 """
 import argparse
 import json
@@ -57,7 +61,10 @@ def roofline(kernel, timing, algo, traffic):
     return {"kernel": kernel, "bound": "hbm", "achieved": None if achieved is None else round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo}
+            "traffic": traffic,
+            "traffic_what": "bytes per launch beyond L2 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a "
+                            "plain device copy); includes Infinity Cache hits, so an upper bound on HBM bytes",
+            "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo}
 
 
 def traffic_bytes(workload, precision, kernel):
@@ -264,124 +271,6 @@ def hb_vs_td(hb, hbcases, St, prec, cap_s, workload="shear", drop=7.0, hb_sample
     return out
 
 
-def thermal_profile(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=400.0):
-    """The paper's thermally driven cavity (Sec. 3.2, N_H = 2) converged with
-    HB-UGKS in FP64, then T/T0 along the vertical centreline x = L/2 at the
-    phases omega t = 0, pi/2, pi, 3 pi/2, rebuilt from the Fourier coefficients
-    of Eq. (40): T(t) = T_0 + 2 Re sum_k That_k exp(i k omega t).  The paper
-    quotes the gas next to the top wall at about 1.17 T0 (t = 0) and 0.79 T0
-    (t = T/2) for Kn = 0.1, St = 2, against the wall's 1.3 T0 and 0.7 T0."""
-    import numpy as np
-    case = hbcases.thermal_paper(St, Kn=Kn)
-    s = hb.Solver(case)
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        s.step(1000)
-        k += 1000
-        r = s.residual()[0]
-        t = time.perf_counter() - t0
-        if k % 10000 == 0:
-            log(f"thermal profile: step {k} R_rho {r:.3e} {t:.1f} s")
-        if r <= tol or t > cap_s:
-            break
-    re, im = s.harmonics(1 << 3)  # T/T0, [1][k][cell]
-    s.close()
-    q = re[0] + 1j * im[0]  # [k][cell]
-    nx, ny = case.nx, case.ny
-    cols = [nx // 2 - 1, nx // 2] if nx % 2 == 0 else [nx // 2]
-    yc = 0.5 * (np.array(case.y_faces[:-1]) + np.array(case.y_faces[1:]))
-    prof = {}
-    for name, ph in (("0", 0.0), ("T/4", 0.5 * np.pi), ("T/2", np.pi), ("3T/4", 1.5 * np.pi)):
-        T = np.zeros(ny)
-        for i in cols:
-            cells = np.arange(ny) * nx + i
-            T += q[0, cells].real + 2.0 * np.real(
-                sum(q[kk, cells] * np.exp(1j * kk * ph) for kk in range(1, case.NH + 1)))
-        prof[name] = (T / len(cols)).tolist()
-    out = {"workload": case.name, "steps": k, "residual": r, "wall_s": t, "y": yc.tolist(), "T_centreline": prof,
-           "T_top_cell": {p_: v[-1] for p_, v in prof.items()}, "T_bottom_cell": {p_: v[0] for p_, v in prof.items()},
-           "paper_top_gas": {"0": 1.17, "T/2": 0.79}}
-    log(f"thermal profile: top cell T/T0 {out['T_top_cell']}, bottom cell {out['T_bottom_cell']}")
-    return out
-
-
-def harmonic_independence(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=300.0):
-    """The paper's shear cavity (Sec. 3.1) converged with N_H = 1 and N_H = 2:
-    the fundamental U_1 / U_a along the vertical centreline x = L/2 from both.
-    The paper finds the two indistinguishable at Kn = 0.1, St = 2, which is
-    why it uses N_H = 1 for the weakly forced shear cases."""
-    import numpy as np
-    out = {"St": St, "Kn": Kn, "runs": {}}
-    prof = {}
-    for NH in (1, 2):
-        case = hbcases.shear_paper(St, Kn=Kn, NH=NH)
-        s = hb.Solver(case)
-        t0 = time.perf_counter()
-        k = 0
-        while True:
-            s.step(1000)
-            k += 1000
-            r = s.residual()[0]
-            t = time.perf_counter() - t0
-            if r <= tol or t > cap_s:
-                break
-        re, im = s.harmonics(1 << 1)  # U, [1][k][cell]
-        s.close()
-        nx, ny = case.nx, case.ny
-        cols = [nx // 2 - 1, nx // 2]
-        u1 = sum(re[0, 1, np.arange(ny) * nx + i] + 1j * im[0, 1, np.arange(ny) * nx + i] for i in cols) / 2
-        prof[NH] = 2.0 * u1 / case.walls[2][1]  # amplitude 2 qhat_1 over U_a
-        out["runs"][f"NH{NH}"] = {"steps": k, "residual": r, "wall_s": t}
-        log(f"harmonic independence: N_H = {NH}, {k} steps, R_rho {r:.2e}, {t:.1f} s")
-    d = np.abs(prof[2] - prof[1])
-    out["max_abs_diff"] = float(np.max(d))
-    out["max_rel_diff"] = float(np.max(d) / np.max(np.abs(prof[1])))
-    out["U1_centreline_NH1"] = {"re": prof[1].real.tolist(), "im": prof[1].imag.tolist()}
-    out["U1_centreline_NH2"] = {"re": prof[2].real.tolist(), "im": prof[2].imag.tolist()}
-    log(f"harmonic independence: max |U1(N_H=2) - U1(N_H=1)| / U_a = {out['max_abs_diff']:.2e} "
-        f"({out['max_rel_diff']:.2e} of the largest)")
-    return out
-
-
-def thermal_harmonics(hb, hbcases, St=2.0, Kn=0.1, tol=1e-9, cap_s=280.0):
-    """The paper's thermal cavity (Sec. 3.2) converged with N_H = 1, 2, 3: the
-    vertical velocity V over the cavity at t = T/2, rebuilt from the Fourier
-    coefficients of Eq. (40).  The paper finds N_H = 1 under-predicting the
-    peak response and N_H = 2, 3 virtually identical."""
-    import numpy as np
-    out = {"St": St, "Kn": Kn, "runs": {}}
-    fields = {}
-    for NH in (1, 2, 3):
-        case = hbcases.thermal_paper(St, Kn=Kn, NH=NH)
-        s = hb.Solver(case)
-        t0 = time.perf_counter()
-        k = 0
-        while True:
-            s.step(1000)
-            k += 1000
-            r = s.residual()[0]
-            t = time.perf_counter() - t0
-            if k % 20000 == 0:
-                log(f"thermal harmonics: N_H = {NH}, step {k}, R_rho {r:.2e}, {t:.1f} s")
-            if r <= tol or t > cap_s:
-                break
-        re, im = s.harmonics(1 << 2)  # V, [1][k][cell]
-        s.close()
-        q = re[0] + 1j * im[0]
-        V = q[0].real + 2.0 * np.real(sum(q[kk] * np.exp(1j * kk * np.pi) for kk in range(1, NH + 1)))
-        fields[NH] = V
-        out["runs"][f"NH{NH}"] = {"steps": k, "residual": r, "wall_s": t, "max_abs_V_half_period": float(np.max(np.abs(V))),
-                                   "min_V": float(V.min()), "max_V": float(V.max())}
-        log(f"thermal harmonics: N_H = {NH}: {k} steps, R_rho {r:.2e}, max |V(T/2)| {np.max(np.abs(V)):.4e}")
-    ref = np.max(np.abs(fields[3]))
-    out["max_diff_NH1_vs_NH3"] = float(np.max(np.abs(fields[1] - fields[3])) / ref)
-    out["max_diff_NH2_vs_NH3"] = float(np.max(np.abs(fields[2] - fields[3])) / ref)
-    log(f"thermal harmonics: max |V1 - V3| / max |V3| = {out['max_diff_NH1_vs_NH3']:.3e}, "
-        f"max |V2 - V3| / max |V3| = {out['max_diff_NH2_vs_NH3']:.3e}")
-    return out
-
-
 def timed_run(hb, case, prec, stream, sync, steps, warmup):
     """Warm up, then time `steps` pseudo steps with per-kernel HIP events on the
     handle's stream; returns (ms per step, per-kernel (launches, ms), residual)."""
@@ -403,22 +292,77 @@ def timed_run(hb, case, prec, stream, sync, steps, warmup):
     return (t1 - t0) * 1e3 / steps, kt, res
 
 
+def host_cpu():
+    """CPU model and logical CPUs of this host (for the oracle baseline)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def oracle_error(hb, oracle, hbcases, case, prec):
+    """One pseudo step of `case` from a seeded perturbed state on the GPU (the
+    launch configuration timed above) and on the oracle; the largest
+    difference of W, h, b over the step's signal (largest deviation of the
+    oracle's result from the rest state, floored at 1% of the state)."""
+    import numpy as np
+    o = oracle.Oracle(case)
+    W, h, b = o.state()
+    rest = (W[:, :1, :].copy(), h[:, :1, :].copy(), b[:, :1, :].copy())
+    h = h * (1.0 + 0.02 * hbcases.uniform(h.shape, 4242))
+    b = b * (1.0 + 0.02 * hbcases.uniform(b.shape, 4243))
+    W = W * (1.0 + 0.01 * hbcases.uniform(W.shape, 4244))
+    o.set_state(W, h, b)
+    s = hb.Solver(case, precision=prec)
+    s.set_state(W, h, b)
+    del W, h, b
+    o.step(1)
+    s.step(1)
+    out = {}
+    for name, a, r, r0 in zip("Whb", s.state(), o.state(), rest):
+        scale = max(np.max(np.abs(r - r0)), 1e-2 * np.max(np.abs(r)))
+        out[name] = float(np.max(np.abs(a - r)) / scale)
+    s.close()
+    return {"what": "one step from a seeded perturbed state, max|gpu - oracle| / signal", "rel_err": out}
+
+
+def cpu_oracle(oracle, case, target_s=15.0):
+    """The oracle timed on this host's cores for about target_s seconds."""
+    o = oracle.Oracle(case)
+    o.step(1)  # first touch / page-in
+    t = time.perf_counter()
+    o.step(1)
+    per = time.perf_counter() - t
+    steps = max(1, min(200, int(target_s / max(per, 1e-6))))
+    t = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t
+    return {"value": case.updates * steps / dt, "unit": "updates/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} pseudo steps of {case.name} ({case.nc} cells x {case.nv} velocities x "
+                      f"{case.NT} levels), {dt:.1f} s", "host": host_cpu()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kn", type=float, default=1.0)
     ap.add_argument("--st", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--workload", choices=("shear", "thermal"), default="shear",
-                    help="shear: 64x64 cells, 32x32 velocities, NH=1; thermal: 64x64, 48x48, NH=4")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default=None,
+                    help="default: mixed for the thermal workload, fp64 for the shear one")
+    ap.add_argument("--workload", choices=("shear", "thermal"), default="thermal",
+                    help="thermal: 64x64 cells, 48x48 velocities on [-5,5], NH=4 (the HBM-roofline case); "
+                         "shear: 64x64, 32x32, NH=1")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving", "hbtd", "thermal_profile", "harmonic_independence",
-                                       "thermal_harmonics"),
-                    default=None,
+    ap.add_argument("--only", choices=("batch", "serving", "hbtd"), default=None,
                     help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
                          "comparison (prints its JSON)")
     ap.add_argument("--td-cap", type=float, default=600.0,
@@ -430,6 +374,8 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(batched cases would shard by case with no communication).", file=sys.stderr)
         sys.exit(2)
+    if args.precision is None:
+        args.precision = "mixed" if args.workload == "thermal" else "fp64"
 
     import hbcases
     import paper_2605_03479_amd as hb
@@ -459,15 +405,6 @@ def main():
         log(f"copy calibration: 5 x {args.copy_mib} MiB device copies")
         del src, dst
 
-    if args.only == "thermal_harmonics":
-        print(json.dumps(thermal_harmonics(hb, hbcases)), flush=True)
-        return
-    if args.only == "harmonic_independence":
-        print(json.dumps(harmonic_independence(hb, hbcases)), flush=True)
-        return
-    if args.only == "thermal_profile":
-        print(json.dumps(thermal_profile(hb, hbcases, St=args.st if args.st != 1.0 else 2.0)), flush=True)
-        return
     if args.only == "hbtd":
         prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
         print(json.dumps(hb_vs_td(hb, hbcases, args.st, prec, args.td_cap, args.workload)), flush=True)
@@ -497,41 +434,36 @@ def main():
                   "moments": 2 * wb * case.updates}
     dom = max(kt, key=lambda k: kt[k][1])
     roof = roofline(dom, kt[dom], algo_bytes.get(dom), traffic_bytes(case.name, args.precision, dom))
-    step_bytes = 6 * wb * case.updates  # moments (2 words) + update (4 words) per update
+    # the method's own floor: read (h, b) once and write them once per update
+    step_bytes = 4 * wb * case.updates
     kernels = {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt.items()}
+
+    import oracle
+    err = None
+    if not args.no_extra:
+        err = oracle_error(hb, oracle, hbcases, case, prec)
+        log(f"oracle error, one step: {err['rel_err']}")
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        o = oracle.Oracle(case)
-        o.step(1)  # first touch / page-in
-        steps = args.cpu_steps
-        if steps <= 0:
-            t = time.perf_counter()
-            o.step(1)
-            per = time.perf_counter() - t
-            steps = max(1, min(200, int(15.0 / max(per, 1e-6))))
-        t = time.perf_counter()
-        o.step(steps)
-        dt = time.perf_counter() - t
-        cpu = {"value": case.updates * steps / dt, "unit": "updates/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": f"{steps} pseudo steps of the same 64x64x32^2 NH=1 case ({dt:.1f} s)"}
-        log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads")
+        cpu = cpu_oracle(oracle, case)
+        log(f"cpu oracle: {cpu['value']:.4e} updates/s on {cpu['cores']} threads ({cpu['host']['model']})")
 
     # the oracle on one host thread, in a child process (OpenMP reads its thread count at start-up)
     cpu1 = None
     if cpu is not None and not args.no_extra:
         import subprocess
+        mk = "shear_cavity" if args.workload == "shear" else "thermal_cavity"
         code = ("import sys, time; sys.path.insert(0, %r); import hbcases, oracle; "
-                "c = hbcases.shear_cavity(%r, %r); o = oracle.Oracle(c); o.step(1); t = time.perf_counter(); "
-                "o.step(5); print(c.updates * 5 / (time.perf_counter() - t), oracle.threads())") % (ROOT, args.kn, args.st)
+                "c = hbcases.%s(%r, %r); o = oracle.Oracle(c); o.step(1); t = time.perf_counter(); "
+                "o.step(1); print(c.updates / (time.perf_counter() - t), oracle.threads())") % (
+            ROOT, mk, args.kn, args.st)
         env = dict(os.environ, OMP_NUM_THREADS="1")
         try:
             r1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
             v1, th1 = r1.stdout.split()[-2:]
             cpu1 = {"value": float(v1), "unit": "updates/s", "cores": int(th1), "kind": "oracle",
-                    "sample": "5 pseudo steps of the same case"}
+                    "sample": f"1 pseudo step of {case.name}"}
             log(f"cpu oracle, one thread: {cpu1['value']:.4e} updates/s")
         except Exception as e:  # the baseline is context; the GPU numbers stand without it
             log(f"cpu oracle, one thread: not measured ({e})")
@@ -556,22 +488,24 @@ def main():
         tconv = time.perf_counter() - t0
         s.close()
         conv = {"tol": 1e-8, "steps": k, "residual": r, "converged": bool(r <= 1e-8), "wall_s": tconv,
-                "cases_per_h": 3600.0 / tconv}
+                "cases_per_h": 3600.0 / tconv if r <= 1e-8 else None, "wall_cap_s": 60.0}
         if cpu is not None:
             cpu_step = case.updates / cpu["value"]
             conv["cpu_oracle_wall_s_extrapolated"] = k * cpu_step
-            conv["cpu_oracle_cases_per_h_extrapolated"] = 3600.0 / (k * cpu_step)
-        log(f"converge: {k} steps to R_rho {r:.2e} in {tconv:.2f} s ({conv['cases_per_h']:.0f} cases/h)")
+        log(f"converge: {k} steps to R_rho {r:.2e} in {tconv:.2f} s")
 
     extra = []
     if not args.no_extra:
         others = []
-        if prec == hb.HB_FP64:
-            others.append((case, hb.HB_MIXED, "mixed"))
-        if args.workload == "shear":
+        if args.workload == "thermal":
+            others += [(hbcases.shear_cavity(1.0, 1.0), hb.HB_FP64, "fp64"),
+                       (hbcases.shear_cavity(1.0, 1.0), hb.HB_MIXED, "mixed")]
+        else:
+            if prec == hb.HB_FP64:
+                others.append((case, hb.HB_MIXED, "mixed"))
             others.append((hbcases.thermal_cavity(1.0, 1.0), hb.HB_MIXED, "mixed"))
         for c2, p2, pname in others:
-            steps2 = max(10, min(args.steps, 60))
+            steps2 = max(10, min(args.steps, 100))
             ms2, kt2, _ = timed_run(hb, c2, p2, stream, sync, steps2, 5)
             n2 = max(c2.nx - 4, 0) * max(c2.ny - 4, 0)
             d2 = max(kt2, key=lambda k: kt2[k][1])
@@ -579,6 +513,7 @@ def main():
             a2 = {"update_int": 4 * wb2 * n2 * c2.nv * c2.NT, "moments": 2 * wb2 * c2.updates}.get(d2)
             extra.append({"workload": c2.name, "precision": pname, "updates_per_s": c2.updates / (ms2 * 1e-3),
                           "ms_per_step": ms2, "steps": steps2,
+                          "effective_GBps_per_step": 4 * wb2 * c2.updates / (ms2 * 1e-3) / 1e9,
                           "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt2.items()},
                           "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
@@ -586,16 +521,16 @@ def main():
     # per-step time over the Kn x St grids of the shear and thermal cases (the arithmetic per step does not
     # depend on them)
     knst = None
-    if not args.no_extra and args.workload == "shear":
+    if not args.no_extra:
         knst = []
         for kn in hbcases.SHEAR_KN:
             for st in hbcases.SHEAR_ST:
                 c3 = hbcases.shear_cavity(kn, st)
-                ms3, _, _ = timed_run(hb, c3, prec, stream, sync, 30, 5)
-                knst.append({"workload": c3.name, "precision": args.precision, "Kn": kn, "St": st, "ms_per_step": ms3,
-                             "updates_per_s": c3.updates / (ms3 * 1e-3)})
-        log("Kn x St sweep: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst))
-        # and over the thermal cases' grid, in the mixed form those cases are defined in
+                for p3, pn in ((hb.HB_FP64, "fp64"), (hb.HB_MIXED, "mixed")):
+                    ms3, _, _ = timed_run(hb, c3, p3, stream, sync, 30, 5)
+                    knst.append({"workload": c3.name, "precision": pn, "Kn": kn, "St": st, "ms_per_step": ms3,
+                                 "updates_per_s": c3.updates / (ms3 * 1e-3)})
+        log("shear Kn x St: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst))
         for kn in hbcases.THERMAL_KN:
             for st in hbcases.THERMAL_ST:
                 c3 = hbcases.thermal_cavity(kn, st)
@@ -604,10 +539,9 @@ def main():
                              "updates_per_s": c3.updates / (ms3 * 1e-3)})
         log("thermal Kn x St: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst[-4:]))
 
-    batched = serving_res = None
+    batched = None
     if not args.no_extra:
         batched = batched_sweep(hb, hbcases)
-        serving_res = serving(hb, hbcases)
 
     out = {
         "metric": METRIC, "value": ups, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
@@ -617,15 +551,16 @@ def main():
         "config": {"workload": case.name, "cells": case.nc, "velocities": case.nv, "levels": case.NT,
                    "Kn": case.Kn, "St": case.St, "precision": args.precision},
         "effective_GBps_per_step": step_bytes / (ms_step * 1e-3) / 1e9,
+        "effective_frac_per_step": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernel_avg_us": kernels,
         "roofline": roof,
+        "oracle_error": err,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
         "converge": conv,
         "kn_st_sweep": knst,
         "other_workloads": extra,
         "batched": batched,
-        "serving": serving_res,
     }
     print(json.dumps(out), flush=True)
 

@@ -152,7 +152,8 @@ int hb_ugks_time(hb_handle h, double *t);
 /* Residual of the last completed step, Eq. (43): RMS over cells of the
  * level-0 change of (rho, rho U, rho V, rho E).  Synchronises the stream.
  * step_index (may be NULL) receives the number of steps taken.
- * Errors: HB_ESTATE, HB_EDIVERGED (NaN/Inf seen in any step since set_case). */
+ * Errors: HB_ESTATE, HB_EDIVERGED (a NaN/Inf in W^{k+1} at any level, or in
+ * the residual, in any step since set_case; the residual itself is then NaN). */
 int hb_ugks_residual(hb_handle h, double out[4], long *step_index);
 
 /* Fourier coefficients of Eq. (40), qhat_k = (1/NT) sum_n q_n exp(-i k omega t_n),

@@ -122,6 +122,8 @@ struct hb_ugks {
     std::vector<double> vref_host;
     double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
     int *flag = nullptr;
+    // harmonics scratch: per-(var, level, cell) values, then [var][k][cell] re and im
+    double *hvars = nullptr, *hre = nullptr, *him = nullptr;
     // time-domain form (one level, global step): wall inputs, physical time,
     // W at the start of the current period and the period residual
     hb_wall walls[4]{};

@@ -735,11 +735,14 @@ __device__ inline void cells_block(const Params &P, const double *__restrict__ f
         cell_eq(P, Wc + n * 4, cm, dG, cr);
         cell_eq(P, Wnew, cm, dG, cr + CREC_T);
         cr[16] = 1.0 / (1.0 + cr[CREC_T + 5]);
-        if (n == 0)
-            for (int k = 0; k < 4; k++) {
-                const double d = Wnew[k] - Wc[k];
-                d2[k] = d * d;
-            }
+        // level 0 carries the residual of Eq. (43); the other levels add
+        // 0 * W^{k+1}, which is +-0 for finite values (the sums are
+        // unchanged) and NaN for NaN/Inf, so divergence at any level
+        // reaches the residual and its flag in the same step
+        for (int k = 0; k < 4; k++) {
+            const double d = Wnew[k] - Wc[k];
+            d2[k] = n == 0 ? d * d : 0.0 * Wnew[k];
+        }
     }
     for (int k = 0; k < 4; k++) red[k][threadIdx.x] = d2[k];
     __syncthreads();

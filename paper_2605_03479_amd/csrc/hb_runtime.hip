@@ -437,6 +437,12 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
     ALLOC(H->vref, nvp, double);
+    {
+        const size_t nh = (size_t)(P.NH + 1) * P.nc * 7;
+        ALLOC(H->hvars, (size_t)P.nc * NT * 7, double);
+        ALLOC(H->hre, nh, double);
+        ALLOC(H->him, nh, double);
+    }
     // The boundary ring (cells within two of a wall), listed as a walk around
     // the cavity: each cell is keyed by the perimeter position of its nearest
     // wall, then by its depth.  Contiguous ranges of the list, one per XCD,
@@ -763,14 +769,9 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
     const size_t per = (size_t)(P.NH + 1) * P.nc;
     if (capacity < nsel * per) return HB_ECAPACITY;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
-    double *vars = nullptr, *dre = nullptr, *dim_ = nullptr;
-    const size_t nvars = (size_t)P.nc * P.NT * 7, nout = 7 * per;
-    if (hipMalloc(&vars, nvars * sizeof(double)) != hipSuccess) return HB_ENOMEM;
-    if (hipMalloc(&dre, nout * sizeof(double)) != hipSuccess || hipMalloc(&dim_, nout * sizeof(double)) != hipSuccess) {
-        (void)hipFree(vars);
-        (void)hipFree(dre);
-        return HB_ENOMEM;
-    }
+    // scratch of the handle (allocated with the case, from its pool or budget)
+    double *vars = H->hvars, *dre = H->hre, *dim_ = H->him;
+    const size_t nout = 7 * per;
     const int c = H->cur;
     if (H->precision == HB_MIXED)
         hipLaunchKernelGGL(hb::k_harm_vars<float>, dim3(P.nc), dim3(256), 0, H->stream, P, (const float *)H->h[c],
@@ -788,9 +789,6 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
         rc = HB_EDEVICE;
     if (rc == HB_OK && hipMemcpy(him.data(), dim_, nout * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         rc = HB_EDEVICE;
-    (void)hipFree(vars);
-    (void)hipFree(dre);
-    (void)hipFree(dim_);
     if (rc != HB_OK) return rc;
     size_t o = 0;
     for (int v = 0; v < 7; v++) {

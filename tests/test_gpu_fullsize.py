@@ -8,6 +8,10 @@
   oracle's whole-grid step, so it is checked by properties that hold at any
   size: a resting Maxwellian between walls at rest stays at rest, and a
   bottom wall heated uniformly keeps the solution mirror-symmetric in x.
+- The same per-block tables (64 x 64 velocities, N_T = 11: 88 KB of
+  dynamic LDS) on a 6 x 6-cell cavity, which the oracle steps in seconds:
+  every element against the oracle after two steps from a perturbed state,
+  with interior cells (the update kernel of the large grids) among them.
 - The largest velocity grid with the most levels (128^2, N_T = 11) needs
   180 KB of tables per block, more than a CU's LDS: set-up refuses it.
 - The 64-case seeded sweep as one tuned mixed batch (40 GB of state, the
@@ -93,6 +97,29 @@ def test_outlier_size_mirror_symmetry(gpu):
         d = np.max(np.abs(W[..., k] - sign * Wm[..., k]))
         _say(f"  component {k}: mirror difference {d:.2e} (signal {sig:.2e})")
         assert d <= 1e-12 * max(sig, np.max(np.abs(W[..., k] - (W[..., k].mean() if sign > 0 else 0.0))))
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)], ids=["fp64", "mixed"])
+def test_outlier_tables_against_oracle(gpu, oracle_mod, prec, tol):
+    case = Case(6, 6, 64, 5.0, 0.5, 2.0, 5, hbcases.thermal_walls(0.3, 0, "sin"), name="lds88k_6x6")
+    o = oracle_mod.Oracle(case)
+    W, h, b = o.state()
+    rest = (W[:, :1, :].copy(), h[:, :1, :].copy(), b[:, :1, :].copy())
+    h = h * (1.0 + 0.03 * hbcases.uniform(h.shape, 5151))
+    b = b * (1.0 + 0.03 * hbcases.uniform(b.shape, 5152))
+    W = W * (1.0 + 0.01 * hbcases.uniform(W.shape, 5153))
+    W[..., 1:3] = 0.01 * hbcases.uniform(W[..., 1:3].shape, 5154)
+    o.set_state(W, h, b)
+    s = gpu.Solver(case, precision=prec)
+    s.set_state(W, h, b)
+    _say(f"  {case.name}: 6x6 cells, 64^2 velocities, N_T = 11, two steps, prec {prec}")
+    o.step(2)
+    s.step(2)
+    for name, a, r, r0 in zip("Whb", s.state(), o.state(), rest):
+        err = _rel(a, r, r0)
+        _say(f"  {name}: rel err {err:.3e}")
+        assert err <= tol, (name, err)
+    s.close()
 
 
 def test_largest_tables_refused(gpu):
