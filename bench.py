@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell·ξ·instance updates/s per pseudo-step (%HBM peak); cases/h; p50/p99"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_amd/csrc/hb_device.h",
-                  "paper_2605_03479_amd/csrc/hb_layout.h")
+                  "paper_2605_03479_amd/csrc/hb_layout.h", "paper_2605_03479_amd/csrc/hb_mixed.h")
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {

@@ -57,6 +57,7 @@ class Case:
     alpha_vss: float = 1.0
     K: int = 1                # internal degrees of freedom
     macro_mode: int = 0       # 0 = macro flux of Eq. (24); 1 = all-discrete sum of the micro flux
+    level_mass: int = 1       # 1 = level-mass projection after each pseudo step (convergence aid), 0 = off
     dt_mode: int = 0          # 0 = local pseudo step (Eqs. 31-32); 1 = global step dt_fixed
     dt_fixed: float = 0.0
     vrule: int = 0            # 1-D velocity rule: 0 = trapezoid on [-umax, umax], 1 = Gauss-Hermite

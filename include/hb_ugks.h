@@ -104,9 +104,22 @@ typedef struct {
     int K_int;                /* internal degrees of freedom (Eq. 3); default 1 */
     int dt_mode;              /* 0 = local pseudo steps (Eqs. 31-32), 1 = global step dt_fixed */
     double dt_fixed;
+    int macro_flux_mode;      /* 0 = macro flux of Eq. (24) (C2, C3 parts as analytic Maxwellian
+                                 moments); 1 = the velocity sum of the micro flux of Eq. (23) */
+    int level_mass;           /* 1 = after every pseudo step scale W, h, b of each level n by
+                                 s_n = Mbar / M_n (M_n the level's mass in the cavity, Mbar
+                                 their mean).  Not in the paper: a convergence aid.  With local
+                                 pseudo steps the level masses drift apart in the transient and
+                                 the explicit spectral source (Eq. 29) rotates the difference
+                                 between levels without damping it, so the residual stalls in
+                                 strongly forced cavities.  Every fixed point of the step has
+                                 equal level masses, so s_n = 1 there and the converged result
+                                 is the same; 0 = the step as printed.  The residual of Eq. (43)
+                                 is the increment before the scaling. */
 } hb_numerics;
 
-/* Defaults: cfl 0.5, face_dt 0, Pr 2/3, omega_vss 0.81, alpha_vss 1, K_int 1, dt_mode 0. */
+/* Defaults: cfl 0.5, face_dt 0, Pr 2/3, omega_vss 0.81, alpha_vss 1, K_int 1, dt_mode 0,
+ * macro_flux_mode 0, level_mass 1. */
 void hb_ugks_default_numerics(hb_numerics *out);
 
 /* Create a handle on opts->device (NULL opts = device 0, null stream, FP64).

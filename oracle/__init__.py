@@ -42,7 +42,7 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_double, _D, _D]
+                                  ctypes.c_double, _D, _D, ctypes.c_int]
         L.hbref_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.hbref_td_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
         L.hbref_residual.argtypes = [ctypes.c_void_p, _D]
@@ -169,7 +169,8 @@ class Oracle:
         rc = lib().hbref_setup(self._h, case.nx, case.ny, case.L, case.H, _p(xf), _p(yf), case.M,
                                case.umax, case.Kn, case.St, NH, _p(walls), case.cfl,
                                case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K,
-                               case.macro_mode, dt_mode, case.dt_fixed, _p(u1), _p(w1))
+                               case.macro_mode, dt_mode, case.dt_fixed, _p(u1), _p(w1),
+                               int(getattr(case, "level_mass", 1)))
         if rc != 0:
             lib().hbref_free(self._h)
             self._h = None

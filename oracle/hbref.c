@@ -46,7 +46,7 @@ typedef struct {
     /* physics and numerics */
     int NH, NT, K;
     double Kn, St, omega, mu_ref, Pr, omega_vss, gamma, cfl;
-    int face_dt, macro_mode, dt_mode;
+    int face_dt, macro_mode, dt_mode, level_mass;
     double dt_fixed;
     double E[NTMAX * NTMAX];
     double wall_ut[4][NTMAX], wall_T[4][NTMAX];
@@ -436,7 +436,7 @@ static void wall_state_at(const hbref *o, int wl, double theta, double *ut, doub
 int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, const double *yf, int M,
                 double umax, double Kn, double St, int NH, const double *walls, double cfl, int face_dt,
                 double Pr, double omega_vss, double alpha_vss, int K, int macro_mode, int dt_mode,
-                double dt_fixed, const double *u1in, const double *w1in)
+                double dt_fixed, const double *u1in, const double *w1in, int level_mass)
 {
     hbref *o = (hbref *)p;
     if (nx < 3 || ny < 3 || M < 2 || (M % 2) != 0 || NH < 0 || 2 * NH + 1 > NTMAX || Kn <= 0.0) return -1;
@@ -459,6 +459,7 @@ int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, 
     o->cfl = cfl;
     o->face_dt = face_dt;
     o->macro_mode = macro_mode;
+    o->level_mass = level_mass;
     o->dt_mode = dt_mode;
     o->dt_fixed = dt_fixed;
     o->mu_ref = mu_ref_from_kn(Kn, omega_vss, alpha_vss);
@@ -990,6 +991,43 @@ static void all_fluxes(hbref *o)
 
 /* One pseudo step k -> k+1 (Sec. 2.4).  In time-domain mode (NT = 1, no E
  * term) the same step is one explicit physical step of size dt_fixed. */
+/* Level-mass projection (a convergence aid; not in the paper).  The spectral
+ * source of Eq. (29) only moves mass between the sub-time levels, and with
+ * local pseudo steps (Eq. 31) the flux terms of the cells no longer cancel in
+ * the sum over the cavity, so each level's total mass M_n drifts during the
+ * transient.  The part of (M_n) that is not level-independent then rotates
+ * under the explicit source term without decaying: the density residual
+ * stalls.  Every fixed point of the step has M_n equal at all levels (sum
+ * Eq. (29) over the cells: the fluxes cancel at impermeable walls and
+ * omega E M = 0 leaves only constants), so the step is followed by a scaling
+ * of W, h and b at each level n by s_n = 1 + (Mbar - M_n) / M_n, Mbar the mean
+ * level mass: s_n = 1 exactly when the masses agree, and the fixed points of
+ * the projected step are those of the step itself.  M_n = sum_i |Omega_i|
+ * rho_{i,n}; the residual of Eq. (43) is the step's increment before the
+ * scaling. */
+static void level_mass_projection(hbref *o)
+{
+    int nc = o->nc, NT = o->NT, nv = o->nv;
+    double M[NTMAX];
+    for (int n = 0; n < NT; n++) {
+        M[n] = 0.0;
+        for (int c = 0; c < nc; c++) M[n] += o->dx[c % o->nx] * o->dy[c / o->nx] * o->W[IDX(c, n) * 4];
+    }
+    double d = 0.0;
+    for (int n = 0; n < NT; n++) d += M[n] - M[0];
+    double mean = M[0] + d / NT;
+    for (int n = 0; n < NT; n++) {
+        double s_n = 1.0 + (mean - M[n]) / M[n];
+        for (int c = 0; c < nc; c++) {
+            for (int k = 0; k < 4; k++) o->W[IDX(c, n) * 4 + k] *= s_n;
+            for (int a = 0; a < nv; a++) {
+                o->h[IDX(c, n) * nv + a] *= s_n;
+                o->b[IDX(c, n) * nv + a] *= s_n;
+            }
+        }
+    }
+}
+
 static void one_step(hbref *o, int with_E)
 {
     int nc = o->nc, NT = o->NT, nv = o->nv, K = o->K;
@@ -1076,6 +1114,7 @@ static void one_step(hbref *o, int with_E)
     o->W = o->Wn;
     o->Wn = t;
     o->step++;
+    if (o->level_mass) level_mass_projection(o);
 }
 
 void hbref_step(void *p, int nsteps)

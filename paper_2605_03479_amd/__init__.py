@@ -44,7 +44,8 @@ class hb_vgrid(ctypes.Structure):
 class hb_numerics(ctypes.Structure):
     _fields_ = [("cfl", ctypes.c_double), ("face_dt", ctypes.c_int), ("Pr", ctypes.c_double),
                 ("omega_vss", ctypes.c_double), ("alpha_vss", ctypes.c_double), ("K_int", ctypes.c_int),
-                ("dt_mode", ctypes.c_int), ("dt_fixed", ctypes.c_double)]
+                ("dt_mode", ctypes.c_int), ("dt_fixed", ctypes.c_double), ("macro_flux_mode", ctypes.c_int),
+                ("level_mass", ctypes.c_int)]
 
 
 class hb_request(ctypes.Structure):
@@ -179,7 +180,7 @@ def _case_args(case):
     walls = (hb_wall * 4)(*[hb_wall(*map(float, w)) for w in case.walls])
     vg = hb_vgrid(case.M, case.umax, case.vrule)
     nm = hb_numerics(case.cfl, case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K, case.dt_mode,
-                     case.dt_fixed)
+                     case.dt_fixed, case.macro_mode, getattr(case, "level_mass", 1))
     return g, walls, vg, nm, (xf, yf)
 
 

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", "hb_lib.hip")]
 DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in ("hb_runtime.hip", "hb_batch.hip")] + [os.path.join(HERE, "csrc", f) for f in ("hb_kernels.h", "hb_batch_kernels.h", "hb_handle.h",
-                                                       "hb_device.h", "hb_layout.h")] + [
+                                                       "hb_device.h", "hb_layout.h", "hb_mixed.h")] + [
     os.path.join(ROOT, "include", "hb_ugks.h")]
 LIB = os.path.join(HERE, "libhbugks.so")
 

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void kb_resid(const CaseDev *__restrict__ cs, 
         const WorkItem w = items[it];
         const CaseDev &C = cs[w.cs];
         const int slot = (int)(ctl[w.cs].kstep % C.ring_len);
-        resid_block(C.rpart, C.cells_blocks, C.P.nc, C.ring, slot, C.flag);
+        resid_block(C.P, C.rpart, C.cells_blocks, C.ring, slot, C.flag);
         __syncthreads();
     }
 }
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256, HB_UPD_WAVES) void kb_update_int(const CaseDev
         const CaseDev &C = cs[w.cs];
         const int cur = ctl[w.cs].cur;
         update_int_cell<NT, TS>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
-                                (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], w.unit);
+                                (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], C.W[1 - cur], w.unit);
         __syncthreads();
     }
 }
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256, 2) void kb_update_bnd(const CaseDev *__restric
         const CaseDev &C = cs[w.cs];
         const int cur = ctl[w.cs].cur;
         update_bnd_cell<NT, TS>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
-                                (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], w.unit);
+                                (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], C.W[1 - cur], w.unit);
         __syncthreads();
     }
 }

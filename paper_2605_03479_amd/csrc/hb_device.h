@@ -30,6 +30,8 @@ __device__ inline gptr<T> G(gptr<T> p)
 
 struct Params {
     int nx, ny, nc, M, Mh, Q, Qp, nvp, NT, NH, K, face_dt, dt_mode;
+    int macro_mode;  // 0: macro flux of Eq. (24); 1: the velocity sum of the micro flux
+    int level_mass;  // 1: level-mass projection after each step (see resid_block)
     int ls;  // level stride of h, b in words (nvp plus padding)
     double omega, mu_ref, omega_vss, Pr, cfl, gamma, umax, dt_fixed;
     double E[HB_NTMAX * HB_NTMAX];
@@ -40,6 +42,14 @@ struct Params {
     const double *u1, *w1, *vu, *vv, *vw;
     const int *viu, *viv;
     const double *vref;  // rest Maxwellian per velocity (mixed storage reference)
+    double *lscale;      // per-level scale factors of the level-mass projection [HB_NTMAX]
+    // mixed form only (null otherwise): FP32 face and collision records, the
+    // projection factors s_n and (s_n - 1)/pi in FP32, E(u_k) = exp(-u_k^2)
+    // in FP64 and FP32, and E of Eq. (17) in FP32
+    float *rx32, *ry32, *cr32, *lscale32;
+    const double *ex64;
+    const float *er32;
+    float Ef[HB_NTMAX * HB_NTMAX];
 };
 
 // W = (rho, rho Un, rho Ut, rho E) -> (rho, Un, Ut, lambda); rho E = rho |U|^2/2 + (2+K) rho/(4 lambda)

@@ -122,6 +122,10 @@ struct hb_ugks {
     std::vector<double> vref_host;
     double *feed = nullptr, *recx = nullptr, *recy = nullptr, *crec = nullptr, *rpart = nullptr, *ring = nullptr;
     int *flag = nullptr;
+    double *lscale = nullptr;  // level-mass projection factors of the last step
+    // mixed form: FP32 face and collision records, E(u_k) = exp(-u_k^2) in FP64 and FP32
+    float *rx32 = nullptr, *ry32 = nullptr, *cr32 = nullptr, *er32 = nullptr;
+    double *ex64 = nullptr;
     // harmonics scratch: per-(var, level, cell) values, then [var][k][cell] re and im
     double *hvars = nullptr, *hre = nullptr, *him = nullptr;
     // time-domain form (one level, global step): wall inputs, physical time,

@@ -368,6 +368,24 @@ __device__ inline void gsums2(const Params &P, double lam, double Un, double Ut,
     }
 }
 
+// Moment table of the normalised face Maxwellian over the velocity grid
+// instead of the plane: N[k] = sqrt(lam/pi) sum_i w_i x_i^k exp(-lam (x_i - Un)^2)
+// from the 1-D sums Gn (over the selected half or all nodes), T likewise from
+// Gt; the internal-energy moments stay analytic (the reduced h, b carry them).
+__device__ inline void disc_momtab(const double Gn[7], const double Gt[7], double lam, int K, MomTab &t)
+{
+    const double r = sqrt(lam / HB_PI);
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        t.N[k] = r * Gn[k];
+        t.T[k] = r * Gt[k];
+    }
+    t.N[7] = t.T[7] = 0.0;
+    t.X[0] = 1.0;
+    t.X[1] = K / (2.0 * lam);
+    t.X[2] = K * (K + 2.0) / (4.0 * lam * lam);
+}
+
 // sum_alpha w u_n psi (H0 + H0+, B0 + B0+) from the 1-D sums of the face Maxwellian.
 __device__ inline void equil_flux_sums(int K, double pref, double lam, const P3 &Ph, const P3 &Pb, const double *Gn,
                                        const double *Gt, double S[4])
@@ -393,6 +411,28 @@ __device__ inline void store_side(double *rec, int side, double lam, double Un, 
     }
     s[23] = c4;
     s[24] = c5;
+}
+
+// FP32 coefficients of one side for the mixed form (record layout in
+// hb_layout.h): y-face cubics in (n, t) = (v, u) are stored in the global
+// (u, v) monomial order, so every face of a cell evaluates them on the same
+// per-velocity monomials.
+__device__ inline void store_side32(float *rec32, int side, bool isx, int K, const P3 &Qh, const P3 &Qb, double c4,
+                                    double c5)
+{
+    constexpr int p10y[10] = {0, 2, 1, 5, 4, 3, 9, 8, 7, 6};
+    float *o = rec32 + REC32_SIDEW * side;
+    const double k0h = (1.0 - c4) / HB_PI, k0b = k0h * 0.5 * K;
+#pragma unroll
+    for (int k = 0; k < 10; k++) {
+        const double qh = isx ? Qh.c[k] : Qh.c[p10y[k]], qb = isx ? Qb.c[k] : Qb.c[p10y[k]];
+        o[k] = static_cast<float>(k == 0 ? qh - k0h : qh);
+        o[10 + k] = static_cast<float>(k == 0 ? qb - k0b : qb);
+    }
+    o[20] = static_cast<float>(k0h);
+    o[21] = static_cast<float>(k0b);
+    o[22] = static_cast<float>(c4);
+    o[23] = static_cast<float>(c5);
 }
 
 // one (face, level) per thread t; x-faces first, then y-faces
@@ -425,6 +465,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
     int cL, cR, lo_end;  // cells on the low/high side (-1 if wall)
     double xL = 0, xF = 0, xR = 0;
     double *rec;
+    float *rec32 = nullptr;  // mixed form only
     if (isx) {
         const int fi = f % (nx + 1), jj = f / (nx + 1);
         cL = fi > 0 ? jj * nx + fi - 1 : -1;
@@ -434,6 +475,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         if (cR >= 0) xR = P.xc[fi];
         lo_end = fi == 0;
         rec = recx + ((long)f * NT + n) * REC;
+        if (P.rx32) rec32 = P.rx32 + ((long)f * NT + n) * REC32;
     } else {
         f -= nfx;
         const int ii = f % nx, fj = f / nx;
@@ -444,6 +486,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         if (cR >= 0) xR = P.yc[fj];
         lo_end = fj == 0;
         rec = recy + ((long)f * NT + n) * REC;
+        if (P.ry32) rec32 = P.ry32 + ((long)f * NT + n) * REC32;
     }
     // global -> face-frame index maps (y-faces: n = v, t = u), applied with
     // compile-time indices so that no array is indexed at run time
@@ -511,20 +554,35 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         mpsi_apsi(t0, 0, 1, at, r3);
         for (int k = 0; k < 4; k++) rhs[k] = -(r1[k] + r2[k] + r3[k]);
         slope_solve(Un, Ut, lam, K, rhs, A);
-        // macro flux
+        double Gn[7], Gt[7];
+        gsums2(P, lam, Un, Ut, Gn, Gt);
+        // macro flux: the C2 and C3 parts as Maxwellian moments (Eq. 24), or
+        // as the velocity sums of the micro flux's C2 and C3 parts
         double c2a[4], c2b[4], c2c[4], c3[4];
-        mpsi_apsi(tp, 2, 0, aL, c2a);
-        mpsi_apsi(tm, 2, 0, aR, c2b);
-        mpsi_apsi(t0, 1, 1, at, c2c);
-        mpsi_apsi(t0, 1, 0, A, c3);
+        if (P.macro_mode == 1) {
+            double Gp[7], Gm[7];
+            gsums(P, lam, Un, 1, Gp);
+            gsums(P, lam, Un, 2, Gm);
+            MomTab d0, dp, dm;
+            disc_momtab(Gn, Gt, lam, K, d0);
+            disc_momtab(Gp, Gt, lam, K, dp);
+            disc_momtab(Gm, Gt, lam, K, dm);
+            mpsi_apsi(dp, 2, 0, aL, c2a);
+            mpsi_apsi(dm, 2, 0, aR, c2b);
+            mpsi_apsi(d0, 1, 1, at, c2c);
+            mpsi_apsi(d0, 1, 0, A, c3);
+        } else {
+            mpsi_apsi(tp, 2, 0, aL, c2a);
+            mpsi_apsi(tm, 2, 0, aR, c2b);
+            mpsi_apsi(t0, 1, 1, at, c2c);
+            mpsi_apsi(t0, 1, 0, A, c3);
+        }
         const double sq = (1.0 - P.Pr) * 4.0 * lam * lam / (5.0 * rho);
         P3 Ph, Pb;
         shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 5.0, Ph);
         shakhov_poly(sq, fs.qn, fs.qt, Un, Ut, lam, K - 3.0, Pb);
         Ph.c[0] += 1.0;
         Pb.c[0] += 1.0;
-        double Gn[7], Gt[7];
-        gsums2(P, lam, Un, Ut, Gn, Gt);
         const double pref = rho * lam / HB_PI;
         double S1[4];
         equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
@@ -569,6 +627,7 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
                 Qb.c[k] *= sbq;
             }
             store_side(rec, side, lam, Un, Ut, Qh, Qb, C[3] * rdG, C[4] * rdG);
+            if (rec32) store_side32(rec32, side, isx, K, Qh, Qb, C[3] * rdG, C[4] * rdG);
         }
     } else {
         // ---------------- diffuse isothermal wall (Eqs. 25-28)
@@ -620,11 +679,13 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
             Qb.c[k] = Pb.c[k] * pref * (K / (2.0 * lam)) * C[0] / dGf;
         }
         store_side(rec, inc_side, lam, Un, Ut, Qh, Qb, C[3] / dGf, C[4] / dGf);
+        if (rec32) store_side32(rec32, inc_side, isx, K, Qh, Qb, C[3] / dGf, C[4] / dGf);
         p3_zero(Qh);
         p3_zero(Qb);
         Qh.c[0] = rw * pw;
         Qb.c[0] = rw * pw * xw;
         store_side(rec, refl_side, lw, 0.0, Uw, Qh, Qb, 0.0, 0.0);
+        if (rec32) store_side32(rec32, refl_side, isx, K, Qh, Qb, 0.0, 0.0);
     }
     // macro flux in the global frame
     if (isx) {
@@ -700,9 +761,12 @@ __device__ inline void cells_block(const Params &P, const double *__restrict__ f
                                    double *__restrict__ rpart, int blk)
 {
     __shared__ double red[4][128];
+    __shared__ double mred[2][HB_NTMAX];
     const int NT = P.NT, nx = P.nx;
     const int t = blk * 128 + threadIdx.x;
     double d2[4] = {0, 0, 0, 0};
+    double mass = 0.0;  // |Omega_i| rho^{k+1}_{i,n} of this thread's (cell, level)
+    int lvl = -1;
     if (t < P.nc * NT) {
         const int c = t / NT, n = t % NT;
         const int i = c % nx, j = c / nx;
@@ -735,6 +799,29 @@ __device__ inline void cells_block(const Params &P, const double *__restrict__ f
         cell_eq(P, Wc + n * 4, cm, dG, cr);
         cell_eq(P, Wnew, cm, dG, cr + CREC_T);
         cr[16] = 1.0 / (1.0 + cr[CREC_T + 5]);
+        if (P.cr32) {
+            // FP32 record of the mixed form: the amplitudes also as deviations
+            // from the rest Maxwellian's (1/pi, K/(2 pi))
+            float *o = P.cr32 + ((long)c * NT + n) * CREC32;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; s2++) {
+                const double *q = cr + CREC_T * s2;
+                float *os = o + CREC32_T * s2;
+                os[0] = static_cast<float>(q[1]);
+                os[1] = static_cast<float>(q[2]);
+                os[2] = static_cast<float>(2.0 * q[0]);
+                os[3] = static_cast<float>(q[3]);
+                os[4] = static_cast<float>(q[3] - 1.0 / HB_PI);
+                os[5] = static_cast<float>(q[4]);
+                os[6] = static_cast<float>(q[4] - 0.5 * P.K / HB_PI);
+                os[7] = static_cast<float>(q[6]);
+                os[8] = static_cast<float>(q[7]);
+            }
+            o[18] = static_cast<float>(cr[5]);
+            o[19] = static_cast<float>(cr[CREC_T + 5]);
+            o[20] = static_cast<float>(1.0 - cr[5]);
+            o[21] = static_cast<float>(cr[16]);
+        }
         // level 0 carries the residual of Eq. (43); the other levels add
         // 0 * W^{k+1}, which is +-0 for finite values (the sums are
         // unchanged) and NaN for NaN/Inf, so divergence at any level
@@ -743,15 +830,27 @@ __device__ inline void cells_block(const Params &P, const double *__restrict__ f
             const double d = Wnew[k] - Wc[k];
             d2[k] = n == 0 ? d * d : 0.0 * Wnew[k];
         }
+        mass = (P.xf[i + 1] - P.xf[i]) * (P.yf[j + 1] - P.yf[j]) * Wnew[0];
+        lvl = n;
     }
     for (int k = 0; k < 4; k++) red[k][threadIdx.x] = d2[k];
+    // per-level mass of the block: a fixed-order shuffle tree per wave, then
+    // wave 0 + wave 1
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int m = 0; m < NT; m++) {
+        double v = lvl == m ? mass : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (lane == 0) mred[wv][m] = v;
+    }
     __syncthreads();
     for (int s = 64; s > 0; s >>= 1) {
         if (threadIdx.x < s)
             for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x < 4) rpart[blk * 4 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 4) rpart[blk * RPART + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < NT) rpart[blk * RPART + 4 + threadIdx.x] = mred[0][threadIdx.x] + mred[1][threadIdx.x];
 }
 
 __global__ __launch_bounds__(128) void k_cells(Params P, const double *__restrict__ feed, const double *__restrict__ recx,
@@ -763,24 +862,53 @@ __global__ __launch_bounds__(128) void k_cells(Params P, const double *__restric
 }
 
 // ---------------------------------------------------------------- K4: residual
-__device__ inline void resid_block(const double *__restrict__ rpart, int nblk, int nc, double *__restrict__ ring,
-                                   int slot, int *__restrict__ flag)
+// The residual of the step (Eq. 43) into the ring, and the scale factors of
+// the level-mass projection (a convergence aid; not in the paper).  The
+// spectral source only moves mass between levels, and with local pseudo
+// steps the flux terms no longer cancel over the cavity, so each level's mass
+// M_n drifts during the transient; the level-dependent part of (M_n) then
+// rotates under the explicit source term without decaying and the residual
+// stalls.  At every fixed point of the step the level masses agree (summing
+// Eq. 29 over the cells leaves omega E M = 0), so scaling level n by
+// s_n = 1 + (Mbar - M_n) / M_n (Mbar their mean; exactly 1 when they agree)
+// keeps the fixed points and removes that rotation.  One block, fixed-order
+// sums of the cells kernel's block partials.
+__device__ inline void resid_block(const Params &P, const double *__restrict__ rpart, int nblk,
+                                   double *__restrict__ ring, int slot, int *__restrict__ flag)
 {
-    __shared__ double red[4][256];
-    double s[4] = {0, 0, 0, 0};
+    __shared__ double red[RPART][256];
+    const int nk = 4 + P.NT;
+    double s[RPART];
+#pragma unroll
+    for (int k = 0; k < RPART; k++) s[k] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256)
-        for (int k = 0; k < 4; k++) s[k] += rpart[b * 4 + k];
-    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = s[k];
+#pragma unroll
+        for (int k = 0; k < RPART; k++)
+            if (k < nk) s[k] += rpart[b * RPART + k];
+#pragma unroll
+    for (int k = 0; k < RPART; k++) red[k][threadIdx.x] = s[k];
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st)
-            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+            for (int k = 0; k < nk; k++) red[k][threadIdx.x] += red[k][threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x < 4) {
-        const double r = sqrt(red[threadIdx.x][0] / nc);
+        const double r = sqrt(red[threadIdx.x][0] / P.nc);
         ring[slot * 4 + threadIdx.x] = r;
         if (!isfinite(r)) atomicOr(flag, 1);
+    }
+    if (threadIdx.x < P.NT) {
+        const int n = threadIdx.x;
+        double d = 0.0;
+        for (int m = 0; m < P.NT; m++) d += red[4 + m][0] - red[4][0];
+        const double mean = red[4][0] + d / P.NT, Mn = red[4 + n][0];
+        const double sn = P.level_mass ? 1.0 + (mean - Mn) / Mn : 1.0;
+        P.lscale[n] = sn;
+        if (P.lscale32) {
+            P.lscale32[n] = static_cast<float>(sn);
+            P.lscale32[HB_NTMAX + n] = static_cast<float>((sn - 1.0) / HB_PI);
+        }
     }
 }
 
@@ -873,8 +1001,17 @@ __device__ inline void build_tables(const Params &P, const gptr<const double> fr
     }
 }
 
+// W^{k+1} of cell c times the level-mass factors (the block that updates
+// the cell's distributions also scales its macroscopic state; nothing else
+// reads W^{k+1} during the update)
+template <int NT>
+__device__ inline void scale_w(const Params &P, double *__restrict__ Wn, int c)
+{
+    if (threadIdx.x < NT * 4) Wn[(long)c * NT * 4 + threadIdx.x] *= P.lscale[threadIdx.x >> 2];
+}
+
 // Spectral source and semi-implicit collision (Eq. 30) for one velocity at all
-// levels, then the store of h^{k+1}, b^{k+1}.
+// levels, then the store of h^{k+1}, b^{k+1} (times the level-mass factor).
 template <int NT, typename TS>
 __device__ inline void collide_store(const Params &P, gptr<const double> cr, const double *ctab, double dG, double u,
                                      double v, int iu, int iv, const double *hk, const double *bk, const double *dh,
@@ -906,8 +1043,9 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
         const double a0 = cc[5], a1 = cc[CREC_T + 5], rden = cc[16];
         const double hnew = (hk[n] - dG * dh[n] - dgw * Eh + a1 * heq[1] + a0 * (heq[0] - hk[n])) * rden;
         const double bnew = (bk[n] - dG * db[n] - dgw * Eb + a1 * beq[1] + a0 * (beq[0] - bk[n])) * rden;
-        stv<TS>(hn, e0 + (long)n * P.ls, hnew, rh);
-        stv<TS>(bn, e0 + (long)n * P.ls, bnew, rb);
+        const double sc = wave_uniform(P.lscale)[n];  // level-mass projection
+        stv<TS>(hn, e0 + (long)n * P.ls, hnew * sc, rh);
+        stv<TS>(bn, e0 + (long)n * P.ls, bnew * sc, rb);
     }
 }
 
@@ -917,16 +1055,17 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
 // up to 256 VGPRs; at three levels the body needs 120 and runs at four.
 #define HB_UPD_WAVES 2
 template <int NT, typename TS>
-__device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+__device__ inline void update_int_cell_d(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                        const double *__restrict__ crec, const double *__restrict__ dtc,
-                                       TS *__restrict__ hn, TS *__restrict__ bn, int ci)
+                                       TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int ci)
 {
     extern __shared__ double tab[];
     const int nxi = P.nx - 4;
     const int i = 2 + ci % nxi, j = 2 + ci / nxi;
     const int M = P.M, nx = P.nx;
     const int c = j * nx + i;
+    scale_w<NT>(P, Wn, c);
     const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
                                       G(recy) + (long)(j * nx + i) * NT * REC,
                                       G(recy) + (long)((j + 1) * nx + i) * NT * REC};
@@ -1064,29 +1203,19 @@ __device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h
     }
 }
 
-template <int NT, typename TS>
-__global__ __launch_bounds__(256, HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
-                                                       const TS *__restrict__ b, const double *__restrict__ recx,
-                                                       const double *__restrict__ recy,
-                                                       const double *__restrict__ crec,
-                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
-                                                       TS *__restrict__ bn)
-{
-    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn,
-                            strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx - 4, P.ny - 4));
-}
 
 // Cells within two of a wall (listed in cells[]): the general stencil with
 // one-sided wall slopes and the diffuse-wall inflow.
 template <int NT, typename TS>
-__device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+__device__ inline void update_bnd_cell_d(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                        const double *__restrict__ crec, const double *__restrict__ dtc,
-                                       TS *__restrict__ hn, TS *__restrict__ bn, int c)
+                                       TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int c)
 {
     extern __shared__ double tab[];
     const int M = P.M, nx = P.nx, ny = P.ny;
     const int i = c % nx, j = c / nx;
+    scale_w<NT>(P, Wn, c);
     const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
                                       G(recy) + (long)(j * nx + i) * NT * REC,
                                       G(recy) + (long)((j + 1) * nx + i) * NT * REC};
@@ -1243,15 +1372,55 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
     }
 }
 
+}  // namespace hb
+#include "hb_mixed.h"
+namespace hb {
+
+// FP64 storage: the FP64 bodies above; mixed storage: the FP32 bodies of hb_mixed.h
+template <int NT, typename TS>
+__device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                       const double *__restrict__ crec, const double *__restrict__ dtc,
+                                       TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int ci)
+{
+    if constexpr (sizeof(TS) == 4)
+        update_int_cell_m<NT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, ci);
+    else
+        update_int_cell_d<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, ci);
+}
+template <int NT, typename TS>
+__device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                       const double *__restrict__ recx, const double *__restrict__ recy,
+                                       const double *__restrict__ crec, const double *__restrict__ dtc,
+                                       TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int c)
+{
+    if constexpr (sizeof(TS) == 4)
+        update_bnd_cell_m<NT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, c);
+    else
+        update_bnd_cell_d<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, c);
+}
+
+template <int NT, typename TS>
+__global__ __launch_bounds__(256, HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
+                                                       const TS *__restrict__ b, const double *__restrict__ recx,
+                                                       const double *__restrict__ recy,
+                                                       const double *__restrict__ crec,
+                                                       const double *__restrict__ dtc, TS *__restrict__ hn,
+                                                       TS *__restrict__ bn, double *__restrict__ Wn)
+{
+    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn,
+                            strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx - 4, P.ny - 4));
+}
+
 template <int NT, typename TS>
 __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
                                                        const TS *__restrict__ h, const TS *__restrict__ b,
                                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
-                                                       TS *__restrict__ bn)
+                                                       TS *__restrict__ bn, double *__restrict__ Wn)
 {
-    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, cells[xcd_cell(blockIdx.x, gridDim.x)]);
+    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, cells[xcd_cell(blockIdx.x, gridDim.x)]);
 }
 
 // ---------------------------------------------------------------- set-up kernels
@@ -1291,6 +1460,18 @@ __global__ void k_vref(Params P, double *vref)
     }
 }
 
+// E(u_k) = exp(-u_k^2) of the 1-D nodes, in FP64 (the reference the mixed
+// form's deviation tables subtract; the same expression as the tables' own
+// exponential at lam = 1, U = 0) and rounded to FP32 (multipliers)
+__global__ void k_etab(Params P, double *ex64, float *er32)
+{
+    for (int k = threadIdx.x; k < P.M; k += blockDim.x) {
+        const double x = P.u1[k], e = exp(-x * x);
+        ex64[k] = e;
+        er32[k] = static_cast<float>(e);
+    }
+}
+
 __device__ inline void dt_thread(const Params &P, const double *W, double *dtc, int c)
 {
     if (c < P.nc) dtc[c] = local_dt(P, W + (long)c * P.NT * 4, c % P.nx, c / P.nx);
@@ -1311,7 +1492,7 @@ __global__ __launch_bounds__(256) void k_dt_resid(Params P, const double *__rest
     if (blockIdx.x + 1 < gridDim.x)
         dt_thread(P, W, dtc, blockIdx.x * 256 + threadIdx.x);
     else
-        resid_block(rpart, nblk, P.nc, ring, slot, flag);
+        resid_block(P, rpart, nblk, ring, slot, flag);
 }
 
 // ---------------------------------------------------------------- harmonics

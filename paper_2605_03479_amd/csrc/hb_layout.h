@@ -25,4 +25,27 @@ constexpr int REC = 56;       // side 0 = velocities with u_n < 0, side 1 = u_n 
 constexpr int CREC_T = 8;
 constexpr int CREC = 20;
 
+// Mixed form (FP32 per-velocity arithmetic on the deviations dh = h - H_ref,
+// db = b - K/2 H_ref from the rest Maxwellian H_ref = exp(-u^2 - v^2)/pi).
+// Every face flux is taken minus u_n H_ref, which is the same at every face
+// and leaves the divergence unchanged, so with the face exponential
+// e = (E_n + dn)(E_t + dt), E(x) = exp(-x^2) and dn, dt from tables,
+//   u_n [e Q + c4 h0 + c5 s] - u_n H_ref
+//     = u_n [E_n E_t Q' + (e - E_n E_t)(Q' + k0) + c4 dh0 + c5 s],
+// Q' = Q - k0, k0 = (1 - c4)/pi (b: (1 - c4) K/(2 pi)).
+// FP32 face record per (face, level), per side at [REC32_SIDEW * side]:
+//   Q'_h[10], Q'_b[10] in the global monomial order 1, u, v, uu, uv, vv, uuu,
+//   uuv, uvv, vvv; k0_h, k0_b, c4, c5.
+constexpr int REC32_SIDEW = 24;
+constexpr int REC32 = 48;
+// FP32 collision record per (cell, level): for W^k at [0..8] and W^{k+1} at
+// [9..17]: U, V, 2 lam, A, A - 1/pi, B = A K/(2 lam), B - K/(2 pi), s q_x,
+// s q_y; then a0 = dG/(2 tau^k), a1 = dG/(2 tau^{k+1}), 1 - a0, 1/(1 + a1).
+constexpr int CREC32_T = 9;
+constexpr int CREC32 = 24;
+
+// per cells-kernel block partial sums, K3 -> K4: [0..3] level-0 squared
+// increments of W (residual of Eq. 43), [4 + n] mass of level n
+constexpr int RPART = 4 + 11;
+
 }  // namespace hb

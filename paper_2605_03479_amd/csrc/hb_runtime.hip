@@ -168,11 +168,11 @@ static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x, hipEv
     TS *hn = (TS *)H->h[x], *bn = (TS *)H->b[x];
     if (H->n_int > 0)
         hipLaunchKernelGGL((hb::k_update_int<NT, TS>), dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, h, b,
-                           H->recx, H->recy, H->crec, H->dt[c], hn, bn);
+                           H->recx, H->recy, H->crec, H->dt[c], hn, bn, H->W[x]);
     if (mid) (void)hipEventRecord(mid, H->stream);
     if (H->n_bnd > 0)
         hipLaunchKernelGGL((hb::k_update_bnd<NT, TS>), dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P,
-                           H->bnd_cells, h, b, H->recx, H->recy, H->crec, H->dt[c], hn, bn);
+                           H->bnd_cells, h, b, H->recx, H->recy, H->crec, H->dt[c], hn, bn, H->W[x]);
 }
 
 template <typename TS>
@@ -220,6 +220,8 @@ void hb_ugks_default_numerics(hb_numerics *o)
     o->K_int = 1;
     o->dt_mode = 0;
     o->dt_fixed = 0.0;
+    o->macro_flux_mode = 0;
+    o->level_mass = 1;
 }
 
 const char *hb_ugks_strerror(int s)
@@ -289,7 +291,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     if (nx < 3 || ny < 3 || M < 4 || M > 128 || (M & 1) || NH < 0 || 2 * NH + 1 > HB_NTMAX || !(Kn > 0.0) ||
         !(St >= 0.0) || (vg->rule != HB_RULE_TRAPEZOID && vg->rule != HB_RULE_GAUSS_HERMITE) ||
         (vg->rule == HB_RULE_TRAPEZOID && !(vg->umax > 0.0)) || !(nm.cfl > 0.0) || nm.K_int < 0 || !(nm.Pr > 0.0) ||
-        (nm.dt_mode == 1 && !(nm.dt_fixed > 0.0)) || !(g->L > 0.0) || !(g->H > 0.0))
+        (nm.dt_mode == 1 && !(nm.dt_fixed > 0.0)) || !(g->L > 0.0) || !(g->H > 0.0) ||
+        (nm.macro_flux_mode != 0 && nm.macro_flux_mode != 1) || (nm.level_mass != 0 && nm.level_mass != 1))
         return HB_EINVAL;
     for (int w = 0; w < 4; w++)
         if (!(walls[w].T_mean - std::hypot(walls[w].T_hat_re, walls[w].T_hat_im) > 0.0)) return HB_EINVAL;
@@ -319,6 +322,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.NT = 2 * NH + 1;
     P.K = nm.K_int;
     P.face_dt = nm.face_dt;
+    P.macro_mode = nm.macro_flux_mode;
+    P.level_mass = nm.level_mass;
     P.dt_mode = nm.dt_mode;
     P.dt_fixed = nm.dt_fixed;
     P.omega = St;  // Eq. (37) with H = sqrt(2 R T0) = 1
@@ -404,7 +409,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     const size_t nel = (size_t)P.nc * NT * P.ls;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     H->cells_blocks = (P.nc * NT + 127) / 128;
-    H->upd_lds = sizeof(double) * 16 * (size_t)NT * M;
+    H->upd_lds = (H->precision == HB_MIXED ? sizeof(float) : sizeof(double)) * 16 * (size_t)NT * M;
     if (H->upd_lds > 160 * 1024) return HB_EINVAL;
     int rc = HB_OK;
 #define ALLOC(ptr, count, T)                                            \
@@ -433,7 +438,16 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     ALLOC(H->recx, nfx * NT * hb::REC, double);
     ALLOC(H->recy, nfy * NT * hb::REC, double);
     ALLOC(H->crec, (size_t)P.nc * NT * hb::CREC, double);
-    ALLOC(H->rpart, (size_t)H->cells_blocks * 4, double);
+    ALLOC(H->rpart, (size_t)H->cells_blocks * hb::RPART, double);
+    // level-mass factors: HB_NTMAX doubles, then (mixed form) s_n and (s_n - 1)/pi in FP32
+    ALLOC(H->lscale, 2 * HB_NTMAX, double);
+    if (H->precision == HB_MIXED) {
+        ALLOC(H->rx32, nfx * NT * hb::REC32, float);
+        ALLOC(H->ry32, nfy * NT * hb::REC32, float);
+        ALLOC(H->cr32, (size_t)P.nc * NT * hb::CREC32, float);
+        ALLOC(H->ex64, M, double);
+        ALLOC(H->er32, M, float);
+    }
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
     ALLOC(H->vref, nvp, double);
@@ -497,6 +511,16 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.viu = H->veli;
     P.viv = H->veli + nvp;
     P.vref = H->vref;
+    P.lscale = H->lscale;
+    if (H->precision == HB_MIXED) {
+        P.rx32 = H->rx32;
+        P.ry32 = H->ry32;
+        P.cr32 = H->cr32;
+        P.lscale32 = (float *)(H->lscale + HB_NTMAX);
+        P.ex64 = H->ex64;
+        P.er32 = H->er32;
+        for (int k = 0; k < NT * NT; k++) P.Ef[k] = static_cast<float>(P.E[k]);
+    }
     {
         const int rcl = update_lds_attr(H->precision, NT, H->upd_lds);
         if (rcl != HB_OK) {
@@ -508,6 +532,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->step = 0;
     const long tot = (long)nel;
     hipLaunchKernelGGL(hb::k_vref, dim3((nvp + 255) / 256), dim3(256), 0, H->stream, P, H->vref);
+    if (H->precision == HB_MIXED)
+        hipLaunchKernelGGL(hb::k_etab, dim3(1), dim3(128), 0, H->stream, P, H->ex64, H->er32);
     for (int s = 0; s < 2; s++) {
         if (H->precision == HB_MIXED)
             hipLaunchKernelGGL(hb::k_init<float>, dim3((tot + 255) / 256), dim3(256), 0, H->stream, P,
@@ -759,19 +785,15 @@ int hb_ugks_state_in(hb_handle H, const double *W, const double *hh, const doubl
     return HB_OK;
 }
 
-int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im, size_t capacity)
+}  // extern "C"
+
+// Harmonics of Eq. (40) into re/im (selected variables in bit order, host
+// memory) through the device scratch vars [nc][NT][7], dre, dim [7][NH+1][nc].
+static int harmonics_into(hb_ugks *H, unsigned var_mask, double *re, double *im, double *vars, double *dre,
+                          double *dim_)
 {
-    if (!H || !re || !im || (var_mask & ~0x7Fu) || !var_mask) return HB_EINVAL;
-    if (!H->has_case) return HB_ESTATE;
     const hb::Params &P = H->P;
-    int nsel = 0;
-    for (int v = 0; v < 7; v++) nsel += (var_mask >> v) & 1;
-    const size_t per = (size_t)(P.NH + 1) * P.nc;
-    if (capacity < nsel * per) return HB_ECAPACITY;
-    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
-    // scratch of the handle (allocated with the case, from its pool or budget)
-    double *vars = H->hvars, *dre = H->hre, *dim_ = H->him;
-    const size_t nout = 7 * per;
+    const size_t per = (size_t)(P.NH + 1) * P.nc, nout = 7 * per;
     const int c = H->cur;
     if (H->precision == HB_MIXED)
         hipLaunchKernelGGL(hb::k_harm_vars<float>, dim3(P.nc), dim3(256), 0, H->stream, P, (const float *)H->h[c],
@@ -780,24 +802,37 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
         hipLaunchKernelGGL(hb::k_harm_vars<double>, dim3(P.nc), dim3(256), 0, H->stream, P, (const double *)H->h[c],
                            (const double *)H->b[c], H->W[c], vars);
     hipLaunchKernelGGL(hb::k_harm_dft, dim3((nout + 255) / 256), dim3(256), 0, H->stream, P, vars, dre, dim_);
-    int rc = HB_OK;
-    if (hipGetLastError() != hipSuccess) rc = HB_EDEVICE;
-    std::vector<double> hre(nout), him(nout);
-    if (rc == HB_OK && (H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize()) != hipSuccess)
-        rc = HB_EDEVICE;
-    if (rc == HB_OK && hipMemcpy(hre.data(), dre, nout * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        rc = HB_EDEVICE;
-    if (rc == HB_OK && hipMemcpy(him.data(), dim_, nout * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        rc = HB_EDEVICE;
-    if (rc != HB_OK) return rc;
+    HIPOK(hipGetLastError());
+    HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
     size_t o = 0;
     for (int v = 0; v < 7; v++) {
         if (!((var_mask >> v) & 1)) continue;
-        std::memcpy(re + o, hre.data() + v * per, per * sizeof(double));
-        std::memcpy(im + o, him.data() + v * per, per * sizeof(double));
+        HIPOK(hipMemcpy(re + o, dre + v * per, per * sizeof(double), hipMemcpyDeviceToHost));
+        HIPOK(hipMemcpy(im + o, dim_ + v * per, per * sizeof(double), hipMemcpyDeviceToHost));
         o += per;
     }
     return HB_OK;
+}
+
+static int harmonics_check(hb_ugks *H, unsigned var_mask, const double *re, const double *im, size_t capacity)
+{
+    if (!H || !re || !im || (var_mask & ~0x7Fu) || !var_mask) return HB_EINVAL;
+    if (!H->has_case) return HB_ESTATE;
+    int nsel = 0;
+    for (int v = 0; v < 7; v++) nsel += (var_mask >> v) & 1;
+    if (capacity < nsel * (size_t)(H->P.NH + 1) * H->P.nc) return HB_ECAPACITY;
+    if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
+    return HB_OK;
+}
+
+extern "C" {
+
+int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im, size_t capacity)
+{
+    const int rc = harmonics_check(H, var_mask, re, im, capacity);
+    if (rc != HB_OK) return rc;
+    // scratch of the handle (allocated with the case, from its pool or budget)
+    return harmonics_into(H, var_mask, re, im, H->hvars, H->hre, H->him);
 }
 
 int hb_ugks_wall_harmonic(hb_handle H, int wall, int var, int k, double out[2])

@@ -38,6 +38,7 @@ def test_strerror_and_defaults(lib):
     assert b"unknown" in lib.hb_ugks_strerror(-99)
     n = hb.default_numerics()
     assert n.cfl == 0.5 and n.face_dt == 0 and abs(n.Pr - 2 / 3) < 1e-15 and n.K_int == 1
+    assert n.macro_flux_mode == 0 and n.level_mass == 1 and n.dt_mode == 0
 
 
 def test_null_and_state_errors(lib):

@@ -1,12 +1,14 @@
 """GPU mixed form (FP32 storage of the deviation of h, b from the rest
-Maxwellian, FP64 arithmetic, moments, W and residual) against the FP64 CPU
-oracle.
+Maxwellian and FP32 per-velocity flux, source and collision arithmetic on
+those deviations; FP64 face and cell records, moment sums, W and residual)
+against the FP64 CPU oracle.
 
-Bounds: per step, the only new error is the FP32 rounding of the stored
-deviation (relative 2^-24 of it), so states agree to 1e-6 of the signal; at
-convergence the macroscopic harmonics agree to 1e-5 of each variable's
-harmonic signal (the stated mixed-precision tolerance), each side converged
-on its own to R_rho <= 1e-8."""
+Bounds: per step, every FP32 product carries a factor of the size of the
+deviation, so each rounding is 2^-24 of the deviation; the update sums a few
+tens of them, so states agree to 1e-6 of the signal; at convergence the
+macroscopic harmonics agree to 1e-5 of each variable's harmonic signal (the
+stated mixed-precision tolerance), each side converged on its own to
+R_rho <= 1e-8."""
 import numpy as np
 import pytest
 

@@ -230,3 +230,17 @@ def test_degenerate_sizes(gpu, oracle_mod, nx, ny, M, NH):
     rest, out = _run_pair(gpu, oracle_mod, case, st, [1, 7])
     for k, sg, so, rg, ro in out:
         _compare_states(sg, so, rest, what=f"{nx}x{ny} M={M} NH={NH} step {k}")
+
+
+@pytest.mark.parametrize("level_mass,macro_mode", [(0, 0), (1, 1), (0, 1)], ids=["as-printed", "discrete-macro",
+                                                                                "as-printed-discrete-macro"])
+def test_step_options(gpu, oracle_mod, level_mass, macro_mode):
+    """The step as printed (no level-mass projection) and the all-discrete
+    macro flux (velocity sum of the micro flux), on the ragged heated cavity,
+    every element after 1, 3 and 12 steps."""
+    case = _ragged().with_(level_mass=level_mass, macro_mode=macro_mode)
+    st = _perturbed(oracle_mod, case, 4711)
+    rest, out = _run_pair(gpu, oracle_mod, case, st, [1, 3, 12])
+    for k, sg, so, rg, ro in out:
+        _compare_states(sg, so, rest, what=f"level_mass {level_mass} macro {macro_mode} step {k}")
+        np.testing.assert_allclose(rg, ro, rtol=0, atol=1e-10 * np.max(ro))

@@ -137,8 +137,10 @@ def test_harmonics_of_a_known_state(oracle_mod):
 
 
 def test_residual_definition(oracle_mod):
-    """Eq. (43): RMS over cells of the level-0 change of each conservative variable."""
-    o = oracle_mod.Oracle(_forced())
+    """Eq. (43): RMS over cells of the level-0 change of each conservative
+    variable, on the step as printed (with the level-mass projection the
+    residual is the step's increment before the scaling)."""
+    o = oracle_mod.Oracle(_forced(level_mass=0))
     o.step(3)
     W0 = o.state()[0]
     o.step(1)
