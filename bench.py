@@ -11,7 +11,7 @@ x level updates per second.
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                   [--precision fp64|mixed] [--workload thermal|shear] [--no-extra] [--copy-mib N]
-                  [--only batch|serving|hbtd] [--td-cap S]
+                  [--only batch|batch_converge|serving|hbtd] [--td-cap S]
 Besides the headline, the JSON line carries: the headline case's one-step
 error against the FP64 oracle at full size, the oracle timed on the host
 (all threads and one), the time to converge from rest, the 64 x 64-cell,
@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell·ξ·instance updates/s per pseudo-step (%HBM peak); cases/h; p50/p99"
 HBM_PEAK_GBS = 8000.0
+# converged cases/h of the 64-case sweep in the batched mixed form (bench.py --only batch_converge);
+# the serving run's Poisson rate is 0.8 of it
+BATCHED_CAPACITY_PER_H = 300.0
 KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_amd/csrc/hb_device.h",
                   "paper_2605_03479_amd/csrc/hb_layout.h", "paper_2605_03479_amd/csrc/hb_mixed.h")
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
@@ -115,52 +118,84 @@ def batched_sweep(hb, hbcases, steps=5):
             "speedup_batched_vs_plain": t_plain / t_batch, "diverged": diverged}
 
 
-def serving(hb, hbcases, check_every=100, max_steps=20000, tol=1e-8):
-    """Serving loop on the seeded request set: converged cases/h of the batched
-    mixed form (all requests present at once) against the plain FP64 solver
-    running them one at a time to the same residual, then p50/p99
-    time-to-converged under Poisson arrivals at 0.8 of the batched capacity."""
-    import numpy as np
-    reqs = hbcases.serving_requests()
-    n = len(reqs)
-    B = hb.Batch(max_cases=n)
-    res, _, wall = hb.serve(B, reqs, [0.0] * n, precision=hb.HB_MIXED, tol=tol, check_every=check_every,
-                            max_steps=max_steps)
-    B.close()
-    conv = sum(1 for r in res if r["status"] == hb.HB_OK)
-    cap = conv / wall
-    t0 = time.perf_counter()
-    conv_plain = 0
-    for c in reqs:
+def batch_converge(hb, hbcases, form, tol=1e-8, check_every=200, max_steps=60000, cap_s=900.0, first=0,
+                   count=64):
+    """The 64-case seeded sweep to R_rho <= tol.  form "batched": all cases
+    present at once in the serving loop, mixed form, each retired when it
+    converges (converged cases/h = converged / wall).  form "plain": the FP64
+    solver on cases [first, first + count) one at a time, residual read every
+    check_every steps, each case capped at max_steps and the whole run at
+    cap_s (cases not reached are listed)."""
+    cases = hbcases.batch_sweep()
+    out = {"workload": "batch_sweep_64_seed260503479", "form": form, "tol": tol, "check_every": check_every,
+           "max_steps": max_steps, "cap_s": cap_s}
+    if form == "batched":
+        B = hb.Batch(max_cases=len(cases))
+        res, _, wall = hb.serve(B, cases, [0.0] * len(cases), precision=hb.HB_MIXED, tol=tol,
+                                check_every=check_every, max_steps=max_steps, var_mask=0x1, max_wall_s=cap_s)
+        B.close()
+        out["cases"] = [{"name": c.name, "updates": c.updates, "status": r["status"], "steps": r["steps"],
+                         "t_done_s": r["t_done"], "R_rho": r["residual"][0]} for c, r in zip(cases, res)]
+        conv = sum(1 for r in res if r["status"] == hb.HB_OK)
+        out.update(converged=conv, wall_s=wall, cases_per_h=3600.0 * conv / wall)
+        log(f"batched mixed: {conv}/{len(cases)} converged in {wall:.1f} s ({out['cases_per_h']:.0f} cases/h)")
+        return out
+    t_run = time.perf_counter()
+    rows = []
+    for idx in range(first, min(first + count, len(cases))):
+        c = cases[idx]
+        if time.perf_counter() - t_run > cap_s:
+            rows.append({"name": c.name, "status": "not run (wall cap)"})
+            continue
         s = hb.Solver(c)
-        k = 0
+        t0 = time.perf_counter()
+        k, r = 0, float("inf")
         while k < max_steps:
             s.step(check_every)
             k += check_every
             try:
-                if s.residual()[0] <= tol:
-                    conv_plain += 1
-                    break
+                r = s.residual()[0]
             except hb.HBError:
+                r = float("nan")
                 break
+            if r <= tol:
+                break
+        dt = time.perf_counter() - t0
         s.close()
-    wall_plain = time.perf_counter() - t0
-    rate = 0.8 * cap
-    arr = hbcases.poisson_arrivals(n, rate)
+        rows.append({"name": c.name, "updates": c.updates, "status": "converged" if r <= tol else "not converged",
+                     "steps": k, "wall_s": dt, "R_rho": r})
+        log(f"plain fp64 {c.name}: {k} steps, R_rho {r:.2e}, {dt:.1f} s")
+    out["cases"] = rows
+    done = [r for r in rows if r["status"] == "converged"]
+    out.update(converged=len(done), wall_s=time.perf_counter() - t_run)
+    return out
+
+
+def serving(hb, hbcases, n=48, rate_per_s=None, cap_s=900.0, check_every=200, max_steps=60000, tol=1e-8):
+    """The serving workload: n seeded requests drawn as the batched sweep with
+    1/16 outliers of 128^2 cells x 64^2 velocities x N_H = 5, arriving as a
+    seeded Poisson process, served in the mixed form with admission by device
+    footprint until each reaches R_rho <= tol; the run is capped at cap_s
+    (requests unconverged or never admitted are listed, not dropped)."""
+    import numpy as np
+    reqs = hbcases.serving_requests(n)
+    arr = hbcases.poisson_arrivals(n, rate_per_s)
     B = hb.Batch(max_cases=n)
-    res2, _, wall2 = hb.serve(B, reqs, arr, precision=hb.HB_MIXED, tol=tol, check_every=check_every,
-                              max_steps=max_steps)
+    res, _, wall = hb.serve(B, reqs, arr, precision=hb.HB_MIXED, tol=tol, check_every=check_every,
+                            max_steps=max_steps, var_mask=0x1, max_wall_s=cap_s)
     B.close()
-    lat = np.array([r["t_done"] - r["arrival"] for r in res2 if r["status"] == hb.HB_OK])
-    out = {"workload": f"serving_{n}_requests_seed260503480", "requests": n, "converged_batched": conv,
-           "converged_plain_fp64": conv_plain,
-           "batched_mixed_cases_per_h": 3600.0 * conv / wall, "plain_fp64_cases_per_h": 3600.0 * conv_plain / wall_plain,
-           "poisson_rate_per_s": rate, "served_under_arrivals": int(len(lat)),
-           "p50_time_to_converged_s": float(np.percentile(lat, 50)) if len(lat) else None,
-           "p99_time_to_converged_s": float(np.percentile(lat, 99)) if len(lat) else None,
-           "arrival_run_wall_s": wall2}
-    log(f"serving: batched {out['batched_mixed_cases_per_h']:.0f} cases/h vs plain {out['plain_fp64_cases_per_h']:.0f}; "
-        f"p50 {out['p50_time_to_converged_s']} s p99 {out['p99_time_to_converged_s']} s")
+    lat = np.array([r["t_done"] - r["arrival"] for r in res if r["status"] == hb.HB_OK])
+    conv = int(len(lat))
+    out = {"workload": f"serving_{n}_requests_seed260503480_arrivals260503481", "requests": n,
+           "poisson_rate_per_s": rate_per_s, "cap_s": cap_s, "check_every": check_every, "wall_s": wall,
+           "converged": conv, "cases_per_h": 3600.0 * conv / wall,
+           "p50_time_to_converged_s": float(np.percentile(lat, 50)) if conv else None,
+           "p99_time_to_converged_s": float(np.percentile(lat, 99)) if conv else None,
+           "requests_detail": [{"name": c.name, "updates": c.updates, "arrival_s": r["arrival"],
+                                "t_admit_s": r["t_admit"], "t_done_s": r["t_done"], "status": r["status"],
+                                "steps": r["steps"], "R_rho": r["residual"][0]} for c, r in zip(reqs, res)]}
+    log(f"serving: {conv}/{n} converged in {wall:.1f} s, {out['cases_per_h']:.0f} cases/h, "
+        f"p50 {out['p50_time_to_converged_s']} s, p99 {out['p99_time_to_converged_s']} s")
     return out
 
 
@@ -362,9 +397,17 @@ def main():
                     help="thermal: 64x64 cells, 48x48 velocities on [-5,5], NH=4 (the HBM-roofline case); "
                          "shear: 64x64, 32x32, NH=1")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=("batch", "serving", "hbtd"), default=None,
-                    help="run only the batched sweep, the serving measurement or the HB-vs-time-domain "
-                         "comparison (prints its JSON)")
+    ap.add_argument("--only", choices=("batch", "batch_converge", "serving", "hbtd"), default=None,
+                    help="run only the batched sweep's step time, the sweep to convergence, the serving "
+                         "measurement or the HB-vs-time-domain comparison (prints its JSON)")
+    ap.add_argument("--form", choices=("batched", "plain"), default="batched",
+                    help="batch_converge: all cases batched (mixed) or one at a time (FP64)")
+    ap.add_argument("--first", type=int, default=0, help="batch_converge plain: first case")
+    ap.add_argument("--count", type=int, default=64, help="batch_converge plain: number of cases")
+    ap.add_argument("--cap", type=float, default=900.0, help="batch_converge / serving: wall-clock cap (s)")
+    ap.add_argument("--requests", type=int, default=48, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="serving: Poisson arrival rate (1/s); default 0.8 x the measured batched capacity")
     ap.add_argument("--td-cap", type=float, default=600.0,
                     help="hbtd: wall-clock cap (s) of each solver's run")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -409,9 +452,16 @@ def main():
         prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
         print(json.dumps(hb_vs_td(hb, hbcases, args.st, prec, args.td_cap, args.workload)), flush=True)
         return
-    if args.only:
-        res = batched_sweep(hb, hbcases) if args.only == "batch" else serving(hb, hbcases)
-        print(json.dumps(res), flush=True)
+    if args.only == "batch":
+        print(json.dumps(batched_sweep(hb, hbcases)), flush=True)
+        return
+    if args.only == "batch_converge":
+        print(json.dumps(batch_converge(hb, hbcases, args.form, cap_s=args.cap, first=args.first,
+                                        count=args.count)), flush=True)
+        return
+    if args.only == "serving":
+        rate = args.rate if args.rate is not None else 0.8 * BATCHED_CAPACITY_PER_H / 3600.0
+        print(json.dumps(serving(hb, hbcases, n=args.requests, rate_per_s=rate, cap_s=args.cap)), flush=True)
         return
 
     prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64

@@ -185,30 +185,32 @@ def batch_sweep(n=64, seed=260503479):
     return out
 
 
-def serving_requests(n=24, seed=260503480, outlier_p=1.0 / 16.0):
-    """Seeded frequency-response requests for the serving loop, drawn like the
-    batched sweep on a scale whose cases converge within seconds: grid side
-    U{12..32}, velocity side U{12..24} (even), NH U{1..2}, Kn log-uniform
-    [0.3, 10], St log-uniform [0.1, 0.5], half shear (lid 0.01, [-4,4]) and
-    half thermal (bottom wall, dT U(0.1, 0.2), [-5,5]); with probability
-    outlier_p an outlier of 48 x 48 cells, 32 x 32 velocities, NH = 3."""
+def serving_requests(n=48, seed=260503480, outlier_p=1.0 / 16.0):
+    """Seeded frequency-response requests of the serving workload: each request
+    is drawn as a case of the batched sweep (grid side U{24..96}, velocity side
+    U{24..48} rounded up to even, NH U{1..4}, Kn log-uniform [0.01, 10], St
+    log-uniform [0.1, 10], even requests shear (lid 0.01, [-4, 4]) and odd ones
+    thermal (bottom wall, dT U(0.1, 0.5), [-5, 5])); with probability outlier_p
+    it is instead an outlier of 128 x 128 cells, 64 x 64 velocities and NH = 5
+    with the same Kn, St and forcing."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for k in range(n):
-        if rng.uniform() < outlier_p:
-            out.append(Case(48, 48, 32, 4.0, 1.0, 0.5, 3, lid_walls(0.01), name=f"req{k}_outlier"))
-            continue
-        N = int(rng.integers(12, 33))
-        M = int(rng.integers(12, 25))
+        outlier = bool(rng.uniform() < outlier_p)
+        N = int(rng.integers(24, 97))
+        M = int(rng.integers(24, 49))
         M += M % 2
-        NH = int(rng.integers(1, 3))
-        Kn = float(10.0 ** rng.uniform(np.log10(0.3), 1.0))
-        St = float(10.0 ** rng.uniform(-1.0, np.log10(0.5)))
+        NH = int(rng.integers(1, 5))
+        Kn = float(10.0 ** rng.uniform(-2.0, 1.0))
+        St = float(10.0 ** rng.uniform(-1.0, 1.0))
+        if outlier:
+            N, M, NH = 128, 64, 5
+        tag = "outlier_" if outlier else ""
         if k % 2 == 0:
-            out.append(Case(N, N, M, 4.0, Kn, St, NH, lid_walls(0.01), name=f"req{k}_shear"))
+            out.append(Case(N, N, M, 4.0, Kn, St, NH, lid_walls(0.01), name=f"req{k}_{tag}shear"))
         else:
-            dT = float(rng.uniform(0.1, 0.2))
-            out.append(Case(N, N, M, 5.0, Kn, St, NH, thermal_walls(dT, 0, "sin"), name=f"req{k}_thermal"))
+            dT = float(rng.uniform(0.1, 0.5))
+            out.append(Case(N, N, M, 5.0, Kn, St, NH, thermal_walls(dT, 0, "sin"), name=f"req{k}_{tag}thermal"))
     return out
 
 

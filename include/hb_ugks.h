@@ -322,10 +322,13 @@ typedef struct {
  * copied out and its memory freed at once) or that reaches max_steps.
  * Admission and checks happen only between chunks, so a request's steps and
  * result are the same alone and in any mix.  Blocks until every request is
- * retired; *wall_s (may be NULL) receives the run's duration.
+ * retired, or until the first check after max_wall_s seconds (> 0; 0 = no
+ * cap): then the resident cases retire as they stand (HB_ESTATE, with their
+ * steps and residual) and requests never admitted keep t_admit = -1 and
+ * status HB_ESTATE.  *wall_s (may be NULL) receives the run's duration.
  * Errors: HB_EINVAL, HB_ESTATE (the batch holds cases), HB_EDEVICE. */
 int hb_serve_run(hb_batch_handle b, const hb_request *req, int n, double tol, int check_every, long max_steps,
-                 hb_result *out, double *wall_s);
+                 double max_wall_s, hb_result *out, double *wall_s);
 
 #ifdef __cplusplus
 }

@@ -125,8 +125,8 @@ def load_library(path=None):
     L.hb_batch_pool_info.argtypes = [vp, szp, szp, szp]
     L.hb_batch_destroy.argtypes = [vp]
     L.hb_batch_destroy.restype = None
-    L.hb_serve_run.argtypes = [vp, ctypes.POINTER(hb_request), ip, dp, ip, ctypes.c_long, ctypes.POINTER(hb_result),
-                               ctypes.POINTER(dp)]
+    L.hb_serve_run.argtypes = [vp, ctypes.POINTER(hb_request), ip, dp, ip, ctypes.c_long, dp,
+                               ctypes.POINTER(hb_result), ctypes.POINTER(dp)]
     L.hb_serve_run.restype = ctypes.c_int
     for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_td_step",
                  "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_wall_harmonic", "hb_ugks_residual",
@@ -522,9 +522,10 @@ class Batch:
 
 # ------------------------------------------------------------- serving
 def serve(batch, cases, arrivals, precision=HB_MIXED, tol=1e-8, check_every=100, max_steps=200000,
-          var_mask=0x7F):
+          var_mask=0x7F, max_wall_s=0.0):
     """Run the serving loop (hb_serve_run) on an empty Batch.  Returns
-    (results: list of dicts, harmonics: list of (re, im) or None, wall seconds)."""
+    (results: list of dicts, harmonics: list of (re, im) or None, wall seconds).
+    max_wall_s > 0 caps the run (resident cases then retire unconverged)."""
     n = len(cases)
     reqs = (hb_request * n)()
     keep = []
@@ -550,8 +551,8 @@ def serve(batch, cases, arrivals, precision=HB_MIXED, tol=1e-8, check_every=100,
         r.re, r.im, r.capacity = _dp(re), _dp(im), re.size
     out = (hb_result * n)()
     wall = ctypes.c_double()
-    _check(load_library().hb_serve_run(batch.b, reqs, n, float(tol), int(check_every), int(max_steps), out,
-                                       ctypes.byref(wall)), "hb_serve_run")
+    _check(load_library().hb_serve_run(batch.b, reqs, n, float(tol), int(check_every), int(max_steps),
+                                       float(max_wall_s), out, ctypes.byref(wall)), "hb_serve_run")
     res = [dict(status=o.status, steps=o.steps, residual=list(o.residual), t_admit=o.t_admit, t_done=o.t_done,
                 arrival=float(t), bytes=o.bytes) for o, t in zip(out, arrivals)]
     return res, [h if r["status"] == HB_OK else None for h, r in zip(harm, res)], wall.value

@@ -767,7 +767,7 @@ double wall_now()
 }  // namespace
 
 extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, double tol, int check_every,
-                            long max_steps, hb_result *out, double *wall_s)
+                            long max_steps, double max_wall_s, hb_result *out, double *wall_s)
 {
     if (!B || (n > 0 && (!req || !out)) || n < 0 || check_every <= 0 || max_steps <= 0 || !(tol > 0.0))
         return HB_EINVAL;
@@ -827,10 +827,13 @@ extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, dou
         if (rc != HB_OK) return rc;
         const int na = hb_batch_residuals(B, res.data(), steps.data(), div.data(), ids.data(), B->max_cases);
         if (na < 0) return na;
+        // past the wall-clock cap every resident case retires as it stands and
+        // the requests not yet admitted are left unserved (HB_ESTATE, t_admit -1)
+        const bool capped = max_wall_s > 0.0 && wall_now() - t0 >= max_wall_s;
         for (int a = 0; a < na; a++) {
             const int cid = ids[a], k = slot_req[cid];
             if (k < 0) continue;
-            const bool conv = res[4 * a] <= tol, bad = div[a] != 0, late = steps[a] >= max_steps;
+            const bool conv = res[4 * a] <= tol, bad = div[a] != 0, late = steps[a] >= max_steps || capped;
             if (!conv && !bad && !late) continue;
             hb_result &o = out[k];
             o.steps = steps[a];
@@ -847,6 +850,11 @@ extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, dou
             o.t_done = wall_now() - t0;
             active--;
             done++;
+        }
+        if (capped) {
+            for (int k = 0; k < n; k++)
+                if (out[k].t_admit < 0.0 && out[k].t_done < 0.0) done++;  // never admitted
+            break;
         }
     }
     if (wall_s) *wall_s = wall_now() - t0;

@@ -110,3 +110,38 @@ def test_mixed_converged_harmonics(gpu, oracle_mod):
         err = np.max(np.abs(hg[v] - ho[v])) / np.max(np.abs(dev))
         _say(f"  var {v}: rel err {err:.3e}")
         assert err <= 1e-5, (v, err)
+
+
+def test_mixed_converged_harmonics_thermal_nh4(gpu):
+    """The mixed form at the heated-cavity benchmark's velocity grid and level
+    count (48^2 velocities on [-5, 5], N_H = 4, Shakhov, bottom wall
+    T0 (1 + 0.5 sin wt)) on 12 x 12 cells, converged from rest to
+    R_rho <= 1e-8, against the oracle's converged harmonics stored in
+    tests/golden/thermal12_v48_nh4_harmonics.txt (written by
+    tests/golden/make_thermal12.py, the oracle at R_rho = 6e-10): rho, U, V, T
+    within 1e-5 of each variable's harmonic signal."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "thermal12_v48_nh4_harmonics.txt")
+    case = Case(12, 12, 48, 5.0, 1.0, 1.0, 4, hbcases.thermal_walls(0.5, 0, "sin"), name="thermal12_v48_nh4")
+    g = np.loadtxt(path).reshape(4, case.NH + 1, 2, case.nc)
+    ho = g[:, :, 0] + 1j * g[:, :, 1]
+    s = gpu.Solver(case, precision=gpu.HB_MIXED)
+    k = 0
+    while True:
+        s.step(100)
+        k += 100
+        r = s.residual()
+        if r[0] <= 1e-8:
+            break
+        assert k <= 8000, r
+    re, im = s.harmonics(0xF)
+    s.close()
+    hg = re + 1j * im
+    _say(f"  mixed GPU converged in {k} steps (the oracle took 2800 to 6e-10)")
+    for v in range(4):
+        dev = ho[v].copy()
+        if v in (0, 3):
+            dev[0] -= 1.0
+        err = np.max(np.abs(hg[v] - ho[v])) / np.max(np.abs(dev))
+        _say(f"  var {v}: rel err {err:.3e}")
+        assert err <= 1e-5, (v, err)
