@@ -177,6 +177,20 @@ int hb_ugks_residual(hb_handle h, double out[4], long *step_index);
  * of re and im.  Synchronises.  Errors: HB_ESTATE, HB_ECAPACITY, HB_EINVAL. */
 int hb_ugks_harmonics_out(hb_handle h, unsigned var_mask, double *re, double *im, size_t capacity);
 
+/* hb_ugks_harmonics_out for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, with the work arrays in a static device array
+ * of 4 Mi doubles (32 MiB) that each GPU holds from the first call until the
+ * process ends, instead of the handle's own scratch.  Allocates no device
+ * memory (no hipMalloc, hipFree or allocating library call).  A case needs
+ * nc*NT*7 + 14*(NH+1)*nc doubles of it: 128 x 128 cells at NT = 11 use 2.6 Mi.
+ * Every call on one GPU uses that GPU's one array, so calls that overlap on a
+ * GPU (other threads, other handles) race; every array element a call reads
+ * is written by that call first.  Synchronises the handle's stream.
+ * Errors: as hb_ugks_harmonics_out, and HB_ENOMEM when the case needs more
+ * scratch than the static array holds. */
+int hb_ugks_harmonics_out_noalloc(hb_handle h, unsigned var_mask, double *re, double *im, size_t capacity);
+
 /* Wall average of one Fourier coefficient, as in the normalised lid
  * amplitudes of Eqs. (41)-(42): <qhat_k>_wall = (1/L_w) sum_i qhat_k,i ds_i
  * over the cells adjacent to the wall (0 bottom, 1 right, 2 top, 3 left), ds_i

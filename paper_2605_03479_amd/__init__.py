@@ -62,7 +62,8 @@ class hb_result(ctypes.Structure):
 
 EXPORTS = ("hb_vgrid_nodes", "hb_ugks_default_numerics", "hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step",
            "hb_ugks_td_step", "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_wall_harmonic",
-           "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in",
+           "hb_ugks_residual", "hb_ugks_harmonics_out", "hb_ugks_harmonics_out_noalloc", "hb_ugks_state_out",
+           "hb_ugks_state_in",
            "hb_ugks_sizes", "hb_ugks_device_bytes", "hb_ugks_enable_timing", "hb_ugks_kernel_times",
            "hb_ugks_destroy", "hb_ugks_strerror",
            "hb_batch_create", "hb_batch_case_bytes", "hb_batch_add", "hb_batch_remove", "hb_batch_set_active",
@@ -97,6 +98,7 @@ def load_library(path=None):
     L.hb_ugks_wall_harmonic.argtypes = [vp, ip, ip, ip, _D]
     L.hb_ugks_residual.argtypes = [vp, _D, ctypes.POINTER(ctypes.c_long)]
     L.hb_ugks_harmonics_out.argtypes = [vp, ctypes.c_uint, _D, _D, sz]
+    L.hb_ugks_harmonics_out_noalloc.argtypes = [vp, ctypes.c_uint, _D, _D, sz]
     L.hb_ugks_state_out.argtypes = [vp, _D, _D, _D, sz]
     L.hb_ugks_state_in.argtypes = [vp, _D, _D, _D]
     L.hb_ugks_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
@@ -130,7 +132,8 @@ def load_library(path=None):
     L.hb_serve_run.restype = ctypes.c_int
     for name in ("hb_ugks_create", "hb_ugks_set_case", "hb_ugks_pseudo_step", "hb_ugks_td_step",
                  "hb_ugks_td_period", "hb_ugks_time", "hb_ugks_wall_harmonic", "hb_ugks_residual",
-                 "hb_ugks_harmonics_out", "hb_ugks_state_out", "hb_ugks_state_in", "hb_ugks_sizes",
+                 "hb_ugks_harmonics_out", "hb_ugks_harmonics_out_noalloc", "hb_ugks_state_out", "hb_ugks_state_in",
+                 "hb_ugks_sizes",
                  "hb_ugks_enable_timing", "hb_ugks_kernel_times", "hb_batch_create", "hb_batch_case_bytes",
                  "hb_batch_add", "hb_batch_remove", "hb_batch_set_active", "hb_batch_step", "hb_batch_residuals",
                  "hb_batch_case", "hb_batch_tune", "hb_batch_shapes", "hb_batch_use_graph", "hb_batch_set_cache_bytes",
@@ -246,6 +249,18 @@ def hb_ugks_harmonics_out(h, var_mask=0x7F):
     re = np.zeros((nsel, NH + 1, nc))
     im = np.zeros((nsel, NH + 1, nc))
     _check(load_library().hb_ugks_harmonics_out(h, var_mask, _dp(re), _dp(im), re.size), "hb_ugks_harmonics_out")
+    return re, im
+
+
+def hb_ugks_harmonics_out_noalloc(h, var_mask=0x7F):
+    """hb_ugks_harmonics_out through the library's static device scratch (no device allocation)."""
+    nx, ny, nc, M, nv, NT = hb_ugks_sizes(h)
+    nsel = bin(var_mask & 0x7F).count("1")
+    NH = (NT - 1) // 2
+    re = np.zeros((nsel, NH + 1, nc))
+    im = np.zeros((nsel, NH + 1, nc))
+    _check(load_library().hb_ugks_harmonics_out_noalloc(h, var_mask, _dp(re), _dp(im), re.size),
+           "hb_ugks_harmonics_out_noalloc")
     return re, im
 
 

@@ -14,6 +14,8 @@
 
 constexpr int HB_RING = 1024;  // residual ring entries per case
 constexpr int HB_NKERN = 6;    // kernels of one pseudo step, in launch order
+constexpr size_t HB_NOALLOC_DOUBLES = (size_t)4 << 20;  // scratch of hb_ugks_harmonics_out_noalloc (32 MiB)
+constexpr int HB_MAX_DEVICES = 64;
 
 struct HbBuf {
     void *p = nullptr;

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -825,6 +826,30 @@ static int harmonics_check(hb_ugks *H, unsigned var_mask, const double *re, cons
     return HB_OK;
 }
 
+// Device scratch of hb_ugks_harmonics_out_noalloc: a file-scope array, so each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) double scratch[HB_NOALLOC_DOUBLES];
+static std::mutex scratch_mu;
+static double *scratch_dev[HB_MAX_DEVICES];
+
+// The scratch address on the current device `dev`, taken once per device.
+static double *scratch_on(int dev)
+{
+    if (dev < 0 || dev >= HB_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        double *p = nullptr;
+        if (hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_dev[dev] = p;
+    }
+    return scratch_dev[dev];
+}
+
 extern "C" {
 
 int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im, size_t capacity)
@@ -833,6 +858,18 @@ int hb_ugks_harmonics_out(hb_handle H, unsigned var_mask, double *re, double *im
     if (rc != HB_OK) return rc;
     // scratch of the handle (allocated with the case, from its pool or budget)
     return harmonics_into(H, var_mask, re, im, H->hvars, H->hre, H->him);
+}
+
+int hb_ugks_harmonics_out_noalloc(hb_handle H, unsigned var_mask, double *re, double *im, size_t capacity)
+{
+    const int rc = harmonics_check(H, var_mask, re, im, capacity);
+    if (rc != HB_OK) return rc;
+    const hb::Params &P = H->P;
+    const size_t nvars = (size_t)P.nc * P.NT * 7, nout = 7 * (size_t)(P.NH + 1) * P.nc;
+    if (nvars + 2 * nout > HB_NOALLOC_DOUBLES) return HB_ENOMEM;
+    double *base = scratch_on(H->device);
+    if (!base) return HB_EDEVICE;
+    return harmonics_into(H, var_mask, re, im, base, base + nvars, base + nvars + nout);
 }
 
 int hb_ugks_wall_harmonic(hb_handle H, int wall, int var, int k, double out[2])
