@@ -43,7 +43,7 @@ __device__ inline void item_range(const int *__restrict__ bstart, int &a, int &e
 }
 
 template <typename TS>
-__global__ __launch_bounds__(256, HB_MOM_WAVES) void kb_moments(const CaseDev *__restrict__ cs, const CaseCtl *__restrict__ ctl,
+__global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_MOM_WAVES_MIXED : HB_MOM_WAVES) void kb_moments(const CaseDev *__restrict__ cs, const CaseCtl *__restrict__ ctl,
                                                   const WorkItem *__restrict__ items, const int *__restrict__ bstart)
 {
     int a, e;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void kb_resid(const CaseDev *__restrict__ cs, 
 }
 
 template <int NT, typename TS>
-__global__ __launch_bounds__(256, HB_UPD_WAVES) void kb_update_int(const CaseDev *__restrict__ cs,
+__global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_WAVES) void kb_update_int(const CaseDev *__restrict__ cs,
                                                                     const CaseCtl *__restrict__ ctl,
                                                                     const WorkItem *__restrict__ items,
                                                                     const int *__restrict__ bstart)

@@ -42,6 +42,7 @@ struct Params {
     const double *u1, *w1, *vu, *vv, *vw;
     const int *viu, *viv;
     const double *vref;  // rest Maxwellian per velocity (mixed storage reference)
+    const double *rmom;  // per quadrant, sum of w u^a v^b H_ref over its velocities, a + b <= 3 (10 each)
     double *lscale;      // per-level scale factors of the level-mass projection [HB_NTMAX]
     // mixed form only (null otherwise): FP32 face and collision records, the
     // projection factors s_n and (s_n - 1)/pi in FP32, E(u_k) = exp(-u_k^2)

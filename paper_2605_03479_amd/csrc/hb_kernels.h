@@ -119,8 +119,8 @@ __device__ inline int wall_mode(int i, int len) { return i == 0 ? 1 : (i == len 
 // combine into the per-face feeds.
 #define K1_ROW 66
 template <typename TS>
-__device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
-                                    double *__restrict__ feed, int c)
+__device__ inline void moments_cell_d(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                      double *__restrict__ feed, int c)
 {
     // LDS rows per reduction pass: 24, so that three blocks' 52 KB buffers
     // fit a CU's 160 KB of LDS
@@ -272,14 +272,27 @@ __device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, c
     }
 }
 
+// the mixed form's moments (FP32 slopes of the stored deviations, FP64 sums)
+__device__ inline void moments_cell_m(const Params &P, const float *__restrict__ h, const float *__restrict__ b,
+                                      double *__restrict__ feed, int c);
+
+template <typename TS>
+__device__ inline void moments_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
+                                    double *__restrict__ feed, int c)
+{
+    if constexpr (sizeof(TS) == 4) moments_cell_m(P, h, b, feed, c);
+    else moments_cell_d<TS>(P, h, b, feed, c);
+}
+
 // Second __launch_bounds__ argument: hipcc reads it as the minimum number of
 // waves per SIMD the kernel must fit, which sets its VGPR budget (512 / waves).
 // The moments kernel: three waves per SIMD, 168 VGPRs (three 256-thread
-// blocks per CU).
+// blocks per CU); the mixed form's, with 41 sums per lane, four (128 VGPRs).
 #define HB_MOM_WAVES 3
+#define HB_MOM_WAVES_MIXED 4
 
 template <typename TS>
-__global__ __launch_bounds__(256, HB_MOM_WAVES) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
+__global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_MOM_WAVES_MIXED : HB_MOM_WAVES) void k_moments(Params P, const TS *__restrict__ h, const TS *__restrict__ b,
                                                  double *__restrict__ feed)
 {
     moments_cell<TS>(P, h, b, feed, strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx, P.ny));
@@ -1054,6 +1067,8 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
 // Minimum waves per SIMD of the interior update (see HB_MOM_WAVES): two, so
 // up to 256 VGPRs; at three levels the body needs 120 and runs at four.
 #define HB_UPD_WAVES 2
+// the mixed form's FP32 interior update: four waves per SIMD (128 VGPRs)
+#define HB_UPD_WAVES_MIXED 4
 template <int NT, typename TS>
 __device__ inline void update_int_cell_d(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
@@ -1401,7 +1416,7 @@ __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h
 }
 
 template <int NT, typename TS>
-__global__ __launch_bounds__(256, HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
+__global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
                                                        const TS *__restrict__ b, const double *__restrict__ recx,
                                                        const double *__restrict__ recy,
                                                        const double *__restrict__ crec,
@@ -1457,6 +1472,29 @@ __global__ void k_vref(Params P, double *vref)
     if (ap < P.nvp) {
         const double u = P.vu[ap], v = P.vv[ap];
         vref[ap] = ((ap % P.Qp) < P.Q) ? exp(-(u * u + v * v)) / HB_PI : 0.0;
+    }
+}
+
+// Per quadrant q (one wave each), the sums over its velocities of
+// w u^a v^b H_ref for the ten monomials of degree <= 3 in the order
+// 1, u, v, uu, uv, vv, uuu, uuv, uvv, vvv: the rest Maxwellian's share of the
+// moment sums, which the mixed form's moments kernel adds to the sums of the
+// stored deviations.  Runs after k_vref.
+__global__ void k_restmom(Params P, double *rmom)
+{
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc[10];
+    for (int k = 0; k < 10; k++) acc[k] = 0.0;
+    for (int r = lane; r < P.Q; r += 64) {
+        const int ap = q * P.Qp + r;
+        const double u = P.vu[ap], v = P.vv[ap], wh = P.vw[ap] * P.vref[ap];
+        const double m[10] = {1.0, u, v, u * u, u * v, v * v, u * u * u, u * u * v, u * v * v, v * v * v};
+        for (int k = 0; k < 10; k++) acc[k] += wh * m[k];
+    }
+    for (int k = 0; k < 10; k++) {
+        double x = acc[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) rmom[q * 10 + k] = x;
     }
 }
 

@@ -162,8 +162,195 @@ __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float 
     }
 }
 
+// Moments of the mixed form (the sums of the moments kernel, Sec. 2.2).  The
+// FEED sums are linear in the reconstructed face values h0 = h_c + sigma d, so
+// each quadrant's sums split into sums over its velocities of the ten
+// monomials w u^a v^b (a + b <= 3) times the stored deviation, times its x
+// slope and times its y slope, plus the rest Maxwellian's share (the same for
+// every cell: P.rmom).  The slopes of h equal the slopes of its deviation
+// (H_ref is the same in every cell) and are taken in FP32 like the update's;
+// every product and sum is FP64.  Per lane and level 41 sums:
+//   S[0..9]   w m_k dh      S[10..19] w m_k sx_h    S[20..29] w m_k sy_h
+//   S[30..32] w m_k db      S[33..35] w m_k sx_b    S[36..38] w m_k sy_b  (k < 3)
+//   S[39]     w u (r^2 s_h + s_b)     S[40] w v (r^2 s_h + s_b)
+// with s = u sx + v sy and r^2 = u^2 + v^2; the 55 per-quadrant rows of the
+// FP64 form follow from them (mom_row).
+constexpr int NMOM_M = 41;
+
+// Row k (0..54) of quadrant q's sums in the layout of the FP64 moments kernel
+// from the 41 reduced sums S, the rest shares R (10) and the face distances.
+__device__ inline double mom_row(const double *S, const double *R, double kb, double dxo, double dyo, int k)
+{
+    if (k < 10) return (S[k] + dxo * S[10 + k]) + R[k];
+    if (k < 13) return (S[30 + k - 10] + dxo * S[33 + k - 10]) + kb * R[k - 10];
+    if (k < 16) return S[20 + k - 13];
+    if (k == 16) return 0.5 * ((S[23] + S[25]) + S[36]);
+    if (k == 17) return S[13] + S[24];
+    if (k == 18) return S[16] + S[27];
+    if (k == 19) return S[17] + S[28];
+    if (k == 20) return 0.5 * S[39];
+    if (k < 31) return (S[k - 21] + dyo * S[20 + k - 21]) + R[k - 21];
+    if (k < 34) return (S[30 + k - 31] + dyo * S[36 + k - 31]) + kb * R[k - 31];
+    if (k < 37) return S[10 + k - 34];
+    if (k == 37) return 0.5 * ((S[13] + S[15]) + S[33]);
+    if (k == 38) return S[14] + S[25];
+    if (k == 39) return S[17] + S[28];
+    if (k == 40) return S[18] + S[29];
+    if (k == 41) return 0.5 * S[40];
+    if (k < 52) return S[k - 42] + R[k - 42];
+    return S[30 + k - 52] + kb * R[k - 52];
+}
+
+__device__ inline void moments_cell_m(const Params &P, const float *__restrict__ h, const float *__restrict__ b,
+                                      double *__restrict__ feed, int c)
+{
+    // LDS rows per reduction pass: 14 (three passes), 31 KB per block, so that
+    // four blocks fit a CU's 160 KB of LDS (the kernel runs four waves per SIMD)
+    constexpr int RPP = 14, NPASS = (NMOM_M + RPP - 1) / RPP;
+    __shared__ double red[4][RPP * K1_ROW];
+    __shared__ double wsum[4][NMOM_M];
+    const int i = c % P.nx, j = c / P.nx;
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int NT = P.NT;
+    const long sx = (long)NT * P.ls, sy = (long)P.nx * NT * P.ls;
+    // neighbour offsets clamped to the cell itself at the walls (the one-sided
+    // slope there does not read them)
+    const int mx = wall_mode(i, P.nx), my = wall_mode(j, P.ny);
+    const long oW = mx == 1 ? 0 : -sx, oE = mx == 2 ? 0 : sx, oS = my == 1 ? 0 : -sy, oN = my == 2 ? 0 : sy;
+    const float rxm = G(P.rcx)[i], rxp = G(P.rcx)[i + 1], rym = G(P.rcy)[j], ryp = G(P.rcy)[j + 1];
+    const int nch = P.Qp / 64;
+    // interior cells (limited slopes both ways) take a copy of the loop
+    // without the wall cases' branches
+    const bool inner = mx == 0 && my == 0;
+    for (int n = 0; n < NT; n++) {
+        double S[NMOM_M];
+#pragma unroll
+        for (int k = 0; k < NMOM_M; k++) S[k] = 0.0;
+        auto body = [&](int ch, auto interior) {
+            const int ap = q * P.Qp + lane + 64 * ch;
+            const double u = G(P.vu)[ap], v = G(P.vv)[ap], w = G(P.vw)[ap];
+            const long e = ((long)c * NT + n) * P.ls + ap;
+            const gptr<const float> hp = G(h + e), bp = G(b + e);
+            const float hc = hp[0], bc = bp[0];
+            const float hW = hp[oW], bW = bp[oW], hE = hp[oE], bE = bp[oE];
+            const float hS = hp[oS], bS = bp[oS], hN = hp[oN], bN = bp[oN];
+            double sxh, sxb, syh, syb;
+            if constexpr (decltype(interior)::value) {
+                sxh = vanleer_f((hc - hW) * rxm, (hE - hc) * rxp);
+                sxb = vanleer_f((bc - bW) * rxm, (bE - bc) * rxp);
+                syh = vanleer_f((hc - hS) * rym, (hN - hc) * ryp);
+                syb = vanleer_f((bc - bS) * rym, (bN - bc) * ryp);
+            } else {
+                sxh = slope_cf(hW, hc, hE, mx, rxm, rxp);
+                sxb = slope_cf(bW, bc, bE, mx, rxm, rxp);
+                syh = slope_cf(hS, hc, hN, my, rym, ryp);
+                syb = slope_cf(bS, bc, bN, my, rym, ryp);
+            }
+            const double dh = hc, db = bc;
+            const double uu = u * u, uv = u * v, vv = v * v;
+            const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
+                                   w * vv * v};
+#pragma unroll
+            for (int k = 0; k < 10; k++) {
+                S[k] += wm[k] * dh;
+                S[10 + k] += wm[k] * sxh;
+                S[20 + k] += wm[k] * syh;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                S[30 + k] += wm[k] * db;
+                S[33 + k] += wm[k] * sxb;
+                S[36 + k] += wm[k] * syb;
+            }
+            const double t = (uu + vv) * (u * sxh + v * syh) + (u * sxb + v * syb);
+            S[39] += wm[1] * t;
+            S[40] += wm[2] * t;
+        };
+        if (inner)
+            for (int ch = 0; ch < nch; ch++) body(ch, std::true_type{});
+        else
+            for (int ch = 0; ch < nch; ch++) body(ch, std::false_type{});
+        // wave reduction through LDS as in the FP64 kernel: RPP rows per pass,
+        // two lanes per row; the wave writes and reads only its own rows
+        double *rb = red[q];
+#pragma unroll
+        for (int half = 0; half < NPASS; half++) {
+            const int k0 = half * RPP, kn = NMOM_M - k0 < RPP ? NMOM_M - k0 : RPP;
+#pragma unroll
+            for (int k = 0; k < RPP; k++)
+                if (k < kn) rb[k * K1_ROW + lane] = S[k0 + k];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int rk = lane & 31;
+            double part = 0.0;
+            if (rk < kn) {
+                const double2 *row = reinterpret_cast<const double2 *>(rb + rk * K1_ROW + (lane & 32));
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int l = 0; l < 16; l += 2) {
+                    const double2 x0 = row[l], x1 = row[l + 1];
+                    s0 += x0.x;
+                    s1 += x0.y;
+                    s2 += x1.x;
+                    s3 += x1.y;
+                }
+                part = (s0 + s1) + (s2 + s3);
+            }
+            const double other = __shfl_down(part, 32);
+            if (lane < kn) wsum[q][k0 + lane] = part + other;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // quadrant rows, then the faces: E = q1 + q3, W = q0 + q2, N = q2 + q3,
+        // S = q0 + q1, cell moments over all four
+        const double kb = 0.5 * P.K;
+        const double dxe = G(P.xf)[i + 1] - G(P.xc)[i], dxw = G(P.xf)[i] - G(P.xc)[i];
+        const double dyn = G(P.yf)[j + 1] - G(P.yc)[j], dys = G(P.yf)[j] - G(P.yc)[j];
+        auto row = [&](int qq, int k) {
+            return mom_row(wsum[qq], P.rmom + 10 * qq, kb, (qq & 1) ? dxe : dxw, (qq & 2) ? dyn : dys, k);
+        };
+        const gptr<double> out = G(feed) + ((long)c * NT + n) * FEED;
+        for (int t = threadIdx.x; t < FEED; t += blockDim.x) {
+            double val;
+            if (t < 21) val = row(1, t) + row(3, t);
+            else if (t < 42) val = row(0, t - 21) + row(2, t - 21);
+            else if (t < 63) val = row(2, t - 42 + 21) + row(3, t - 42 + 21);
+            else if (t < 84) val = row(0, t - 63 + 21) + row(1, t - 63 + 21);
+            else val = ((row(0, t - 84 + 42) + row(1, t - 84 + 42)) + row(2, t - 84 + 42)) + row(3, t - 84 + 42);
+            out[t] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// van Leer slope of the differences d1 = f_i - f_{i-1}, d2 = f_{i+1} - f_i with
+// reciprocal centre distances r1, r2, divided by 2 r1 r2 (the caller folds
+// that constant into the slope's uses): d1 d2 / (r1 d1 + r2 d2) for d1 d2 > 0.
+__device__ inline float vlslope(float d1, float d2, float r1, float r2)
+{
+    const float p = d1 * d2;
+    const float q = p * __builtin_amdgcn_rcpf(fmaf(r1, d1, r2 * d2));
+    return p > 0.0f ? q : 0.0f;
+}
+
+// a pointer every lane holds, moved to scalar registers
+__device__ inline const float *uniform_ptr(const float *p)
+{
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    return reinterpret_cast<const float *>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // Interior cell (2 <= i <= nx-3, 2 <= j <= ny-3) of the mixed form: the
-// straight-line stencil of update_int_cell in FP32.
+// straight-line stencil of update_int_cell in FP32.  The stencil is read with
+// buffer loads (one descriptor per array at the cell's lowest stencil element,
+// the velocity as the lane offset, level and neighbour as a wave-uniform
+// offset).  The upwind neighbour U's limited slope is taken on the differences
+// away from the cell, dA = f_U - f_UU and dB = f_c - f_U, whatever the
+// quadrant: for u < 0 that negates both differences, so the slope changes sign
+// and the sign goes into the constants that multiply it.
 template <int NT>
 __device__ inline void update_int_cell_m(const Params &P, const float *__restrict__ h, const float *__restrict__ b,
                                          const double *__restrict__ recx, const double *__restrict__ recy,
@@ -199,6 +386,12 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
     cfloat *cc = wave_uniform_f(P.cr32 + (long)c * NT * CREC32);
     const float *rxw = P.rx32 + fw * REC32, *rxe = P.rx32 + fe * REC32, *rys = P.ry32 + fs * REC32,
                 *ryn = P.ry32 + fn * REC32;
+    // the stencil of an interior cell reaches two rows down at most
+    const long lo = (long)c * NT * P.ls - 2 * sy;
+    const __amdgpu_buffer_rsrc_t rsh = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(h + lo), 0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(b + lo), 0, -1, 0x00020000);
+    // the folded van Leer constants 2 r1 r2 of the cell's own slopes
+    const float kx = 2.0f * rx1 * rx2, ky = 2.0f * ry1 * ry2;
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
@@ -213,71 +406,72 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
         const int fxo = su ? 1 : 0, fxi = 1 - fxo, fyo = sv ? 3 : 2, fyi = 5 - fyo;
         const float *bxo = su ? rxe : rxw, *bxi = su ? rxw : rxe, *byo = sv ? ryn : rys, *byi = sv ? rys : ryn;
         const long oU = su ? -sx : sx, oV = sv ? -sy : sy;
-        const float dxo = su ? dxe : dxw, dyo = sv ? dye : dyw;
-        const float dxi = su ? dxiW : dxiE, dyi = sv ? dyiS : dyiN;
-        const float rUm = su ? rx0 : rx2, rUp = su ? rx1 : rx3, rVm = sv ? ry0 : ry2, rVp = sv ? ry1 : ry3;
+        // reciprocal centre distances of U's far (UU to U) and near (U to c)
+        // differences, and V's
+        const float rUf = su ? rx0 : rx3, rUn = su ? rx1 : rx2, rVf = sv ? ry0 : ry3, rVn = sv ? ry1 : ry2;
+        // slopes come as slope / (2 r1 r2); their uses take the factor, with
+        // the upwind neighbours' sign
+        const float kU = (su ? 2.0f : -2.0f) * rUf * rUn, kV = (sv ? 2.0f : -2.0f) * rVf * rVn;
+        const float dxo = (su ? dxe : dxw) * kx, dyo = (sv ? dye : dyw) * ky;
+        const float dxi = (su ? dxiW : dxiE) * kU, dyi = (sv ? dyiS : dyiN) * kV;
+        const float ukx = u * kx, vky = v * ky, ukU = u * kU, vkV = v * kV;
         // |u| rdx, |v| rdy: the divergence is |u| (g_downwind - g_upwind) / dx + ...
         const float aur = fabsf(u) * rdx, avr = fabsf(v) * rdy;
         float hk[NT], bk[NT], dh[NT], db[NT];
         const long e0 = (long)c * NT * P.ls + ap;
+        const unsigned vo = (unsigned)ap * 4u;
         struct Lv {
-            float hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
+            float hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUU, bUU, hUs, bUs, hUn, bUn, hVV, bVV, hVw, bVw, hVe, bVe;
         };
-        auto ld_level = [&](int n) {
+        auto ld_level = [=](int n) {
             Lv L;
-            const gptr<const float> hp = G(h + e0 + (long)n * P.ls), bp = G(b + e0 + (long)n * P.ls);
-            L.hc = hp[0];
-            L.bc = bp[0];
-            L.hW = hp[-sx];
-            L.bW = bp[-sx];
-            L.hE = hp[sx];
-            L.bE = bp[sx];
-            L.hS = hp[-sy];
-            L.bS = bp[-sy];
-            L.hN = hp[sy];
-            L.bN = bp[sy];
-            L.hUF = hp[2 * oU];
-            L.bUF = bp[2 * oU];
-            L.hUs = hp[oU - sy];
-            L.bUs = bp[oU - sy];
-            L.hUn = hp[oU + sy];
-            L.bUn = bp[oU + sy];
-            L.hVF = hp[2 * oV];
-            L.bVF = bp[2 * oV];
-            L.hVw = hp[oV - sx];
-            L.bVw = bp[oV - sx];
-            L.hVe = hp[oV + sx];
-            L.bVe = bp[oV + sx];
+            const int cn = (int)((long)n * P.ls + 2 * sy);
+            auto at = [=](__amdgpu_buffer_rsrc_t rs, long off) -> float {
+                return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)((cn + off) * 4), 0));
+            };
+            L.hc = at(rsh, 0);
+            L.bc = at(rsb, 0);
+            L.hW = at(rsh, -sx);
+            L.bW = at(rsb, -sx);
+            L.hE = at(rsh, sx);
+            L.bE = at(rsb, sx);
+            L.hS = at(rsh, -sy);
+            L.bS = at(rsb, -sy);
+            L.hN = at(rsh, sy);
+            L.bN = at(rsb, sy);
+            L.hUU = at(rsh, 2 * oU);
+            L.bUU = at(rsb, 2 * oU);
+            L.hUs = at(rsh, oU - sy);
+            L.bUs = at(rsb, oU - sy);
+            L.hUn = at(rsh, oU + sy);
+            L.bUn = at(rsb, oU + sy);
+            L.hVV = at(rsh, 2 * oV);
+            L.bVV = at(rsb, 2 * oV);
+            L.hVw = at(rsh, oV - sx);
+            L.bVw = at(rsb, oV - sx);
+            L.hVe = at(rsh, oV + sx);
+            L.bVe = at(rsb, oV + sx);
             return L;
         };
-        // the next level's stencil is loaded before this level's arithmetic
-        Lv nxt = ld_level(0);
 #pragma unroll
         for (int n = 0; n < NT; n++) {
-            const Lv L = nxt;
-            if (n + 1 < NT) nxt = ld_level(n + 1);
+            const Lv L = ld_level(n);
             hk[n] = L.hc;
             bk[n] = L.bc;
-            const float sxh = vanleer_f((L.hc - L.hW) * rx1, (L.hE - L.hc) * rx2);
-            const float sxb = vanleer_f((L.bc - L.bW) * rx1, (L.bE - L.bc) * rx2);
-            const float syh = vanleer_f((L.hc - L.hS) * ry1, (L.hN - L.hc) * ry2);
-            const float syb = vanleer_f((L.bc - L.bS) * ry1, (L.bN - L.bc) * ry2);
-            const float sh = fmaf(u, sxh, v * syh), sb = fmaf(u, sxb, v * syb);
-            // upwind x-neighbour U: its x-slope from (U-1, U, U+1); for su the far value is U-1 and c is U+1
-            const float hU = su ? L.hW : L.hE, bU = su ? L.bW : L.bE;
-            const float xm_h = su ? L.hUF : L.hc, xp_h = su ? L.hc : L.hUF;
-            const float xm_b = su ? L.bUF : L.bc, xp_b = su ? L.bc : L.bUF;
-            const float sxhU = vanleer_f((hU - xm_h) * rUm, (xp_h - hU) * rUp);
-            const float sxbU = vanleer_f((bU - xm_b) * rUm, (xp_b - bU) * rUp);
-            const float syhU = vanleer_f((hU - L.hUs) * ry1, (L.hUn - hU) * ry2);
-            const float sybU = vanleer_f((bU - L.bUs) * ry1, (L.bUn - bU) * ry2);
-            const float hV = sv ? L.hS : L.hN, bV = sv ? L.bS : L.bN;
-            const float ym_h = sv ? L.hVF : L.hc, yp_h = sv ? L.hc : L.hVF;
-            const float ym_b = sv ? L.bVF : L.bc, yp_b = sv ? L.bc : L.bVF;
-            const float syhV = vanleer_f((hV - ym_h) * rVm, (yp_h - hV) * rVp);
-            const float sybV = vanleer_f((bV - ym_b) * rVm, (yp_b - bV) * rVp);
-            const float sxhV = vanleer_f((hV - L.hVw) * rx1, (L.hVe - hV) * rx2);
-            const float sxbV = vanleer_f((bV - L.bVw) * rx1, (L.bVe - bV) * rx2);
+            const float sxh = vlslope(L.hc - L.hW, L.hE - L.hc, rx1, rx2);
+            const float sxb = vlslope(L.bc - L.bW, L.bE - L.bc, rx1, rx2);
+            const float syh = vlslope(L.hc - L.hS, L.hN - L.hc, ry1, ry2);
+            const float syb = vlslope(L.bc - L.bS, L.bN - L.bc, ry1, ry2);
+            const float sh = fmaf(ukx, sxh, vky * syh), sb = fmaf(ukx, sxb, vky * syb);
+            const float hU = su ? L.hW : L.hE, bU = su ? L.bW : L.bE, hV = sv ? L.hS : L.hN, bV = sv ? L.bS : L.bN;
+            const float sxhU = vlslope(hU - L.hUU, L.hc - hU, rUf, rUn);
+            const float sxbU = vlslope(bU - L.bUU, L.bc - bU, rUf, rUn);
+            const float syhU = vlslope(hU - L.hUs, L.hUn - hU, ry1, ry2);
+            const float sybU = vlslope(bU - L.bUs, L.bUn - bU, ry1, ry2);
+            const float syhV = vlslope(hV - L.hVV, L.hc - hV, rVf, rVn);
+            const float sybV = vlslope(bV - L.bVV, L.bc - bV, rVf, rVn);
+            const float sxhV = vlslope(hV - L.hVw, L.hVe - hV, rx1, rx2);
+            const float sxbV = vlslope(bV - L.bVw, L.bVe - bV, rx1, rx2);
             const float *tbx = tabf + (fxo * NT + n) * 3 * M, *tbxi = tabf + (fxi * NT + n) * 3 * M;
             const float *tby = tabf + (fyo * NT + n) * 3 * M, *tbyi = tabf + (fyi * NT + n) * 3 * M;
             cfloat *rxo = wave_uniform_f(bxo + n * REC32 + REC32_SIDEW * su);
@@ -290,12 +484,14 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
             face_g(ryo, m, erv, eru, href, tby[iv], tby[(1 + sv) * M + iu], fmaf(syh, dyo, L.hc),
                    fmaf(syb, dyo, L.bc), sh, sb, gyo_h, gyo_b);
             face_g(rxi, m, eru, erv, href, tbxi[iu], tbxi[(1 + su) * M + iv], fmaf(sxhU, dxi, hU),
-                   fmaf(sxbU, dxi, bU), fmaf(u, sxhU, v * syhU), fmaf(u, sxbU, v * sybU), gxi_h, gxi_b);
+                   fmaf(sxbU, dxi, bU), fmaf(ukU, sxhU, vky * syhU), fmaf(ukU, sxbU, vky * sybU), gxi_h, gxi_b);
             face_g(ryi, m, erv, eru, href, tbyi[iv], tbyi[(1 + sv) * M + iu], fmaf(syhV, dyi, hV),
-                   fmaf(sybV, dyi, bV), fmaf(u, sxhV, v * syhV), fmaf(u, sxbV, v * sybV), gyi_h, gyi_b);
+                   fmaf(sybV, dyi, bV), fmaf(ukx, sxhV, vkV * syhV), fmaf(ukx, sxbV, vkV * sybV), gyi_h, gyi_b);
             dh[n] = fmaf(aur, gxo_h - gxi_h, avr * (gyo_h - gyi_h));
             db[n] = fmaf(aur, gxo_b - gxi_b, avr * (gyo_b - gyi_b));
-            __builtin_amdgcn_sched_barrier(0);
+            // few levels: keep each level's loads and arithmetic together (the
+            // scheduler's interleaving across levels measured slower there)
+            if constexpr (NT <= 5) __builtin_amdgcn_sched_barrier(0);
         }
         collide_store_m<NT>(P, cc, ctab, dG, dgw, m, eru, erv, href, iu, iv, hk, bk, dh, db, hn, bn, e0);
     }

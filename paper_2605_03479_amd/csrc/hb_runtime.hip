@@ -451,7 +451,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     }
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
-    ALLOC(H->vref, nvp, double);
+    // rest Maxwellian per velocity, then its per-quadrant moment sums (4 x 10)
+    ALLOC(H->vref, nvp + 40, double);
     {
         const size_t nh = (size_t)(P.NH + 1) * P.nc * 7;
         ALLOC(H->hvars, (size_t)P.nc * NT * 7, double);
@@ -512,6 +513,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.viu = H->veli;
     P.viv = H->veli + nvp;
     P.vref = H->vref;
+    P.rmom = H->vref + nvp;
     P.lscale = H->lscale;
     if (H->precision == HB_MIXED) {
         P.rx32 = H->rx32;
@@ -533,6 +535,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     H->step = 0;
     const long tot = (long)nel;
     hipLaunchKernelGGL(hb::k_vref, dim3((nvp + 255) / 256), dim3(256), 0, H->stream, P, H->vref);
+    hipLaunchKernelGGL(hb::k_restmom, dim3(1), dim3(256), 0, H->stream, P, H->vref + nvp);
     if (H->precision == HB_MIXED)
         hipLaunchKernelGGL(hb::k_etab, dim3(1), dim3(128), 0, H->stream, P, H->ex64, H->er32);
     for (int s = 0; s < 2; s++) {

@@ -5,8 +5,9 @@ benchmark shape on a grid the oracle converges in minutes.
 Case: 12 x 12 cells, 48 x 48 velocities on [-5, 5], N_H = 4 (nine levels),
 Shakhov (Pr = 2/3), Kn = 1, St = 1, bottom wall T = T0 (1 + 0.5 sin wt), other
 walls at T0, default numerics (CFL 0.5, min face step, level-mass projection),
-from rest to R_rho <= 1e-9 (one decade below the convergence threshold, so the
-stored state is within the GPU run's own convergence error of its fixed point).
+from rest to R_rho <= 1e-11.  (Stopping at the usual 1e-8 leaves this case about
+3e-5 of its density signal away from the fixed point, more than the mixed
+form's 1e-5 bound; at 1e-11 the stored state is within 1e-7 of it.)
 
 The values come from the oracle alone (this script imports nothing but the
 oracle and the case definitions).  Run: python tests/golden/make_thermal12.py
@@ -41,7 +42,7 @@ def main():
         r = o.residual()
         if k % 2000 == 0:
             print(f"step {k}: R_rho {r[0]:.3e} ({time.time() - t0:.0f} s)", flush=True)
-        if r[0] <= 1e-9:
+        if r[0] <= 1e-11:
             break
         if k >= 60000:
             raise RuntimeError(f"no convergence: R = {r}")
