@@ -29,9 +29,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell·ξ·instance updates/s per pseudo-step (%HBM peak); cases/h; p50/p99"
 HBM_PEAK_GBS = 8000.0
-# converged cases/h of the 64-case sweep in the batched mixed form (bench.py --only batch_converge);
+# converged cases/h of the 64-case sweep in the batched mixed form (bench.py --only batch_converge:
+# 64 of 64 converged in 781 s);
 # the serving run's Poisson rate is 0.8 of it
-BATCHED_CAPACITY_PER_H = 300.0
+BATCHED_CAPACITY_PER_H = 295.0
 KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_amd/csrc/hb_device.h",
                   "paper_2605_03479_amd/csrc/hb_layout.h", "paper_2605_03479_amd/csrc/hb_mixed.h")
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
@@ -160,6 +161,8 @@ def batch_converge(hb, hbcases, form, tol=1e-8, check_every=200, max_steps=60000
                 break
             if r <= tol:
                 break
+            if k % (10 * check_every) == 0:
+                log(f"plain fp64 {c.name}: {k} steps, R_rho {r:.2e}")
         dt = time.perf_counter() - t0
         s.close()
         rows.append({"name": c.name, "updates": c.updates, "status": "converged" if r <= tol else "not converged",
@@ -455,6 +458,8 @@ def main():
     if args.only == "batch":
         print(json.dumps(batched_sweep(hb, hbcases)), flush=True)
         return
+    if args.only in ("batch_converge", "serving"):
+        os.environ.setdefault("HB_SERVE_PROGRESS", "1")  # the serving loop's per-chunk lines on stderr
     if args.only == "batch_converge":
         print(json.dumps(batch_converge(hb, hbcases, args.form, cap_s=args.cap, first=args.first,
                                         count=args.count)), flush=True)

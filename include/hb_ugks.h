@@ -340,6 +340,9 @@ typedef struct {
  * cap): then the resident cases retire as they stand (HB_ESTATE, with their
  * steps and residual) and requests never admitted keep t_admit = -1 and
  * status HB_ESTATE.  *wall_s (may be NULL) receives the run's duration.
+ * With the environment variable HB_SERVE_PROGRESS set to a value other than
+ * "0", the loop writes one line to stderr after each chunk (elapsed seconds,
+ * resident cases, requests finished).
  * Errors: HB_EINVAL, HB_ESTATE (the batch holds cases), HB_EDEVICE. */
 int hb_serve_run(hb_batch_handle b, const hb_request *req, int n, double tol, int check_every, long max_steps,
                  double max_wall_s, hb_result *out, double *wall_s);

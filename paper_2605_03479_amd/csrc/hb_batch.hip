@@ -10,6 +10,8 @@
 // on the batch itself and remembers the winner per (precision, N_T, N_v).
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -784,6 +786,8 @@ extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, dou
         int rc = hb_batch_case_bytes(B, req[k].precision, &req[k].geo, req[k].n_harmonics, &req[k].vg, &need[k]);
         if (rc != HB_OK) return rc;
     }
+    const char *pv = std::getenv("HB_SERVE_PROGRESS");
+    const bool progress = pv && *pv && std::strcmp(pv, "0") != 0;
     const double t0 = wall_now();
     int done = 0, next = 0, active = 0;
     std::vector<char> pending(n, 0);
@@ -850,6 +854,11 @@ extern "C" int hb_serve_run(hb_batch_handle B, const hb_request *req, int n, dou
             o.t_done = wall_now() - t0;
             active--;
             done++;
+        }
+        if (progress) {
+            std::fprintf(stderr, "serve: %.1f s, %d resident, %d of %d requests finished\n", wall_now() - t0, active,
+                         done, n);
+            std::fflush(stderr);
         }
         if (capped) {
             for (int k = 0; k < n; k++)

@@ -50,6 +50,7 @@ struct Params {
     float *rx32, *ry32, *cr32, *lscale32;
     const double *ex64;
     const float *er32;
+    const float *vel32;  // vu, vv, vw rounded to FP32 (multipliers of the deviations in the moment sums)
     float Ef[HB_NTMAX * HB_NTMAX];
 };
 

@@ -105,6 +105,11 @@ struct HbPool {
 struct hb_ugks {
     int device = 0;
     hipStream_t stream = nullptr;
+    // the boundary-ring update runs beside the interior update on this stream
+    // (created on first use, default priority), forked from and joined to
+    // `stream` by the two events
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int precision = HB_FP64;
     size_t budget = 0;
     size_t bytes = 0;
@@ -126,7 +131,7 @@ struct hb_ugks {
     int *flag = nullptr;
     double *lscale = nullptr;  // level-mass projection factors of the last step
     // mixed form: FP32 face and collision records, E(u_k) = exp(-u_k^2) in FP64 and FP32
-    float *rx32 = nullptr, *ry32 = nullptr, *cr32 = nullptr, *er32 = nullptr;
+    float *rx32 = nullptr, *ry32 = nullptr, *cr32 = nullptr, *er32 = nullptr, *vel32 = nullptr;
     double *ex64 = nullptr;
     // harmonics scratch: per-(var, level, cell) values, then [var][k][cell] re and im
     double *hvars = nullptr, *hre = nullptr, *him = nullptr;

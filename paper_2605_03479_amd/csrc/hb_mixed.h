@@ -168,8 +168,11 @@ __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float 
 // monomials w u^a v^b (a + b <= 3) times the stored deviation, times its x
 // slope and times its y slope, plus the rest Maxwellian's share (the same for
 // every cell: P.rmom).  The slopes of h equal the slopes of its deviation
-// (H_ref is the same in every cell) and are taken in FP32 like the update's;
-// every product and sum is FP64.  Per lane and level 41 sums:
+// (H_ref is the same in every cell) and are taken in FP32 like the update's.
+// The monomials multiply deviations only, so they are formed from the
+// velocities rounded to FP32 (a relative error of 2^-24 of the deviation sums,
+// the size of the deviations' own storage rounding; the rest share uses the
+// FP64 velocities); every product and sum is FP64.  Per lane and level 41 sums:
 //   S[0..9]   w m_k dh      S[10..19] w m_k sx_h    S[20..29] w m_k sy_h
 //   S[30..32] w m_k db      S[33..35] w m_k sx_b    S[36..38] w m_k sy_b  (k < 3)
 //   S[39]     w u (r^2 s_h + s_b)     S[40] w v (r^2 s_h + s_b)
@@ -219,37 +222,62 @@ __device__ inline void moments_cell_m(const Params &P, const float *__restrict__
     const long oW = mx == 1 ? 0 : -sx, oE = mx == 2 ? 0 : sx, oS = my == 1 ? 0 : -sy, oN = my == 2 ? 0 : sy;
     const float rxm = G(P.rcx)[i], rxp = G(P.rcx)[i + 1], rym = G(P.rcy)[j], ryp = G(P.rcy)[j + 1];
     const int nch = P.Qp / 64;
+    const float *vu = P.vel32, *vv = P.vel32 + P.nvp, *vw = P.vel32 + 2 * (long)P.nvp;
+    // One lane's stencil and velocity for (level n, chunk ch).  (Loading the
+    // next pair ahead needs registers the four waves per SIMD do not leave:
+    // it spills and measured slower.)
+    struct Ld {
+        float u, v, w, hc, bc, hW, bW, hE, bE, hS, bS, hN, bN;
+    };
+    auto load = [&](int n, int ch) {
+        Ld d;
+        const int ap = q * P.Qp + lane + 64 * ch;
+        d.u = vu[ap];
+        d.v = vv[ap];
+        d.w = vw[ap];
+        const long e = ((long)c * NT + n) * P.ls + ap;
+        const gptr<const float> hp = G(h + e), bp = G(b + e);
+        d.hc = hp[0];
+        d.bc = bp[0];
+        d.hW = hp[oW];
+        d.bW = bp[oW];
+        d.hE = hp[oE];
+        d.bE = bp[oE];
+        d.hS = hp[oS];
+        d.bS = bp[oS];
+        d.hN = hp[oN];
+        d.bN = bp[oN];
+        return d;
+    };
     // interior cells (limited slopes both ways) take a copy of the loop
     // without the wall cases' branches
     const bool inner = mx == 0 && my == 0;
+
     for (int n = 0; n < NT; n++) {
         double S[NMOM_M];
 #pragma unroll
         for (int k = 0; k < NMOM_M; k++) S[k] = 0.0;
         auto body = [&](int ch, auto interior) {
-            const int ap = q * P.Qp + lane + 64 * ch;
-            const double u = G(P.vu)[ap], v = G(P.vv)[ap], w = G(P.vw)[ap];
-            const long e = ((long)c * NT + n) * P.ls + ap;
-            const gptr<const float> hp = G(h + e), bp = G(b + e);
-            const float hc = hp[0], bc = bp[0];
-            const float hW = hp[oW], bW = bp[oW], hE = hp[oE], bE = bp[oE];
-            const float hS = hp[oS], bS = bp[oS], hN = hp[oN], bN = bp[oN];
+            const Ld d = load(n, ch);
+
+            const float hc = d.hc, bc = d.bc;
             double sxh, sxb, syh, syb;
             if constexpr (decltype(interior)::value) {
-                sxh = vanleer_f((hc - hW) * rxm, (hE - hc) * rxp);
-                sxb = vanleer_f((bc - bW) * rxm, (bE - bc) * rxp);
-                syh = vanleer_f((hc - hS) * rym, (hN - hc) * ryp);
-                syb = vanleer_f((bc - bS) * rym, (bN - bc) * ryp);
+                sxh = vanleer_f((hc - d.hW) * rxm, (d.hE - hc) * rxp);
+                sxb = vanleer_f((bc - d.bW) * rxm, (d.bE - bc) * rxp);
+                syh = vanleer_f((hc - d.hS) * rym, (d.hN - hc) * ryp);
+                syb = vanleer_f((bc - d.bS) * rym, (d.bN - bc) * ryp);
             } else {
-                sxh = slope_cf(hW, hc, hE, mx, rxm, rxp);
-                sxb = slope_cf(bW, bc, bE, mx, rxm, rxp);
-                syh = slope_cf(hS, hc, hN, my, rym, ryp);
-                syb = slope_cf(bS, bc, bN, my, rym, ryp);
+                sxh = slope_cf(d.hW, hc, d.hE, mx, rxm, rxp);
+                sxb = slope_cf(d.bW, bc, d.bE, mx, rxm, rxp);
+                syh = slope_cf(d.hS, hc, d.hN, my, rym, ryp);
+                syb = slope_cf(d.bS, bc, d.bN, my, rym, ryp);
             }
+            const double u = d.u, v = d.v, w = d.w;
             const double dh = hc, db = bc;
-            const double uu = u * u, uv = u * v, vv = v * v;
-            const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv, w * uu * u, w * uu * v, w * u * vv,
-                                   w * vv * v};
+            const double uu = u * u, uv = u * v, vv2 = v * v;
+            const double wm[10] = {w, w * u, w * v, w * uu, w * uv, w * vv2, w * uu * u, w * uu * v, w * u * vv2,
+                                   w * vv2 * v};
 #pragma unroll
             for (int k = 0; k < 10; k++) {
                 S[k] += wm[k] * dh;
@@ -262,7 +290,7 @@ __device__ inline void moments_cell_m(const Params &P, const float *__restrict__
                 S[33 + k] += wm[k] * sxb;
                 S[36 + k] += wm[k] * syb;
             }
-            const double t = (uu + vv) * (u * sxh + v * syh) + (u * sxb + v * syb);
+            const double t = (uu + vv2) * (u * sxh + v * syh) + (u * sxb + v * syb);
             S[39] += wm[1] * t;
             S[40] += wm[2] * t;
         };

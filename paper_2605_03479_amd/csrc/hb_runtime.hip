@@ -167,13 +167,29 @@ static void launch_update_t(hb_ugks *H, const hb::Params &P, int c, int x, hipEv
 {
     const TS *h = (const TS *)H->h[c], *b = (const TS *)H->b[c];
     TS *hn = (TS *)H->h[x], *bn = (TS *)H->b[x];
+    // The two kernels write disjoint cells from the same inputs.  The ring's
+    // launch is small (a few hundred blocks): on the side stream it fills the
+    // slots the interior launch leaves free instead of running after it.
+    const bool fork = H->n_int > 0 && H->n_bnd > 0 && H->side;
+    hipStream_t sb = fork ? H->side : H->stream;
+    if (fork) {
+        (void)hipEventRecord(H->fork, H->stream);
+        (void)hipStreamWaitEvent(H->side, H->fork, 0);
+    }
+    if (fork)
+        hipLaunchKernelGGL((hb::k_update_bnd<NT, TS>), dim3(H->n_bnd), dim3(256), H->upd_lds, sb, P, H->bnd_cells, h,
+                           b, H->recx, H->recy, H->crec, H->dt[c], hn, bn, H->W[x]);
     if (H->n_int > 0)
         hipLaunchKernelGGL((hb::k_update_int<NT, TS>), dim3(H->n_int), dim3(256), H->upd_lds, H->stream, P, h, b,
                            H->recx, H->recy, H->crec, H->dt[c], hn, bn, H->W[x]);
     if (mid) (void)hipEventRecord(mid, H->stream);
-    if (H->n_bnd > 0)
+    if (fork) {
+        (void)hipEventRecord(H->join, H->side);
+        (void)hipStreamWaitEvent(H->stream, H->join, 0);
+    } else if (H->n_bnd > 0) {
         hipLaunchKernelGGL((hb::k_update_bnd<NT, TS>), dim3(H->n_bnd), dim3(256), H->upd_lds, H->stream, P,
                            H->bnd_cells, h, b, H->recx, H->recy, H->crec, H->dt[c], hn, bn, H->W[x]);
+    }
 }
 
 template <typename TS>
@@ -276,6 +292,12 @@ void hb_ugks_destroy(hb_handle H)
     (void)hipSetDevice(H->device);
     if (H->stream) (void)hipStreamSynchronize(H->stream);
     else (void)hipDeviceSynchronize();
+    if (H->side) {
+        (void)hipStreamSynchronize(H->side);
+        (void)hipStreamDestroy(H->side);
+        (void)hipEventDestroy(H->fork);
+        (void)hipEventDestroy(H->join);
+    }
     free_case(H);
     for (auto &e : H->tev) (void)hipEventDestroy(e);
     delete H;
@@ -448,6 +470,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
         ALLOC(H->cr32, (size_t)P.nc * NT * hb::CREC32, float);
         ALLOC(H->ex64, M, double);
         ALLOC(H->er32, M, float);
+        ALLOC(H->vel32, vel.size(), float);
     }
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
     ALLOC(H->flag, 1, int);
@@ -493,6 +516,10 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     if (H->count_only) return HB_OK;
     HIPOK(hipMemcpy(H->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(H->vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (H->precision == HB_MIXED) {
+        std::vector<float> v32(vel.begin(), vel.end());
+        HIPOK(hipMemcpy(H->vel32, v32.data(), v32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     HIPOK(hipMemcpy(H->veli, veli.data(), veli.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPOK(hipMemset(H->flag, 0, sizeof(int)));
     HIPOK(hipMemcpy(H->bnd_cells, bnd.data(), bnd.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -522,6 +549,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
         P.lscale32 = (float *)(H->lscale + HB_NTMAX);
         P.ex64 = H->ex64;
         P.er32 = H->er32;
+        P.vel32 = H->vel32;
         for (int k = 0; k < NT * NT; k++) P.Ef[k] = static_cast<float>(P.E[k]);
     }
     {
@@ -558,9 +586,30 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
 }  // extern "C"
 
 // Queue one step of Sec. 2.4 on the handle's stream and swap the buffers.
+// the side stream and its fork/join events, on the handle's device
+static int side_stream(hb_ugks *H)
+{
+    if (H->side) return HB_OK;
+    if (hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking) != hipSuccess) {
+        H->side = nullptr;
+        return HB_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&H->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&H->join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(H->side);
+        H->side = nullptr;
+        return HB_EDEVICE;
+    }
+    return HB_OK;
+}
+
 static int enqueue_step(hb_ugks *H)
 {
     const hb::Params &P = H->P;
+    if (H->n_bnd > 0 && H->n_int > 0) {
+        const int rc = side_stream(H);
+        if (rc != HB_OK) return rc;
+    }
     const int NT = P.NT;
     const int nfaces = (P.nx + 1) * P.ny + P.nx * (P.ny + 1);
     const int c = H->cur, x = 1 - c;
