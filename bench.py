@@ -601,7 +601,7 @@ def main():
     out = {
         "metric": METRIC, "value": ups, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == hb.HB_FP64 else "f32-storage/f64-arith",
+        "vs_baseline": None, "dtype": "f64" if prec == hb.HB_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": case.name, "cells": case.nc, "velocities": case.nv, "levels": case.NT,
                    "Kn": case.Kn, "St": case.St, "precision": args.precision},
