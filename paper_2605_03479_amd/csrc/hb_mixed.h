@@ -560,6 +560,12 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
     cfloat *cc = wave_uniform_f(P.cr32 + (long)c * NT * CREC32);
     const float *rxw = P.rx32 + fw * REC32, *rxe = P.rx32 + fe * REC32, *rys = P.ry32 + fs * REC32,
                 *ryn = P.ry32 + fn * REC32;
+    // buffer loads as in the interior update: one descriptor per array based
+    // two rows below the cell (the lowest element a ring stencil can reach; the
+    // descriptor's base may lie below the array, every address read is inside)
+    const long lo = (long)c * NT * P.ls - 2 * sy;
+    const __amdgpu_buffer_rsrc_t rsh = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(h + lo), 0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(b + lo), 0, -1, 0x00020000);
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
@@ -590,42 +596,44 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
         const float aur = fabsf(u) * rdx, avr = fabsf(v) * rdy;
         float hk[NT], bk[NT], dh[NT], db[NT];
         const long e0 = (long)c * NT * P.ls + ap;
+        const unsigned vo = (unsigned)ap * 4u;
         struct Lv {
             float hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
         };
-        auto ld_level = [&](int n) {
+        auto ld_level = [=](int n) {
             Lv L;
-            const gptr<const float> hp = G(h + e0 + (long)n * P.ls), bp = G(b + e0 + (long)n * P.ls);
-            L.hc = hp[0];
-            L.bc = bp[0];
-            L.hW = hp[oW];
-            L.bW = bp[oW];
-            L.hE = hp[oE];
-            L.bE = bp[oE];
-            L.hS = hp[oS];
-            L.bS = bp[oS];
-            L.hN = hp[oN];
-            L.bN = bp[oN];
-            L.hUF = hp[oUc + oUF];
-            L.bUF = bp[oUc + oUF];
-            L.hUs = hp[oUc + oS];
-            L.bUs = bp[oUc + oS];
-            L.hUn = hp[oUc + oN];
-            L.bUn = bp[oUc + oN];
-            L.hVF = hp[oVc + oVF];
-            L.bVF = bp[oVc + oVF];
-            L.hVw = hp[oVc + oW];
-            L.bVw = bp[oVc + oW];
-            L.hVe = hp[oVc + oE];
-            L.bVe = bp[oVc + oE];
+            const int cn = (int)((long)n * P.ls + 2 * sy);
+            auto at = [=](__amdgpu_buffer_rsrc_t rs, long off) -> float {
+                return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)((cn + off) * 4), 0));
+            };
+            L.hc = at(rsh, 0);
+            L.bc = at(rsb, 0);
+            L.hW = at(rsh, oW);
+            L.bW = at(rsb, oW);
+            L.hE = at(rsh, oE);
+            L.bE = at(rsb, oE);
+            L.hS = at(rsh, oS);
+            L.bS = at(rsb, oS);
+            L.hN = at(rsh, oN);
+            L.bN = at(rsb, oN);
+            L.hUF = at(rsh, oUc + oUF);
+            L.bUF = at(rsb, oUc + oUF);
+            L.hUs = at(rsh, oUc + oS);
+            L.bUs = at(rsb, oUc + oS);
+            L.hUn = at(rsh, oUc + oN);
+            L.bUn = at(rsb, oUc + oN);
+            L.hVF = at(rsh, oVc + oVF);
+            L.bVF = at(rsb, oVc + oVF);
+            L.hVw = at(rsh, oVc + oW);
+            L.bVw = at(rsb, oVc + oW);
+            L.hVe = at(rsh, oVc + oE);
+            L.bVe = at(rsb, oVc + oE);
             return L;
         };
-        Lv nxt = ld_level(0);
         constexpr int UNR = NT <= 3 ? NT : 1;
 #pragma unroll UNR
         for (int n = 0; n < NT; n++) {
-            const Lv L = nxt;
-            if (n + 1 < NT) nxt = ld_level(n + 1);
+            const Lv L = ld_level(n);
             const float hc = L.hc, bc = L.bc;
             hk[n] = hc;
             bk[n] = bc;
