@@ -38,17 +38,17 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "01c235d4cb5149e4",
+    "sources_sha256_16": "90f5e144ed813039",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 263843921,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 627508200,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73647365,
-        "shear64_v32_nh1_kn1_st1/mixed/moments": 143719223,
-        "shear64_v32_nh1_kn1_st1/mixed/update_int": 307585339,
-        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38170065,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1175654889,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2877582818,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 452747898,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 264848896,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 633992499,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73621402,
+        "shear64_v32_nh1_kn1_st1/mixed/moments": 152891494,
+        "shear64_v32_nh1_kn1_st1/mixed/update_int": 250026496,
+        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38390272,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1080128205,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2240970342,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 270912819,
     },
 }
 

@@ -187,6 +187,10 @@ struct hb_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the boundary-ring updates run beside the interior updates on this
+    // stream (default priority), forked and joined per cache group
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int num_cu = 256;
     HbPool pool;
     int max_cases = 0;
@@ -370,7 +374,16 @@ static void enqueue_step(hb_batch *B)
         if (cg.resid.grid)
             hipLaunchKernelGGL(hb::kb_resid, dim3(cg.resid.grid), dim3(256), 0, st, cs, ctl, cg.resid.d_items,
                                cg.resid.d_bstart);
-        for (auto &g : cg.groups) launch_group(g, cs, ctl, st);
+        if (B->side) {
+            (void)hipEventRecord(B->fork, st);
+            (void)hipStreamWaitEvent(B->side, B->fork, 0);
+            for (auto &g : cg.groups) launch_group(g, cs, ctl, B->side, false, true);
+            for (auto &g : cg.groups) launch_group(g, cs, ctl, st, true, false);
+            (void)hipEventRecord(B->join, B->side);
+            (void)hipStreamWaitEvent(st, B->join, 0);
+        } else {
+            for (auto &g : cg.groups) launch_group(g, cs, ctl, st);
+        }
     }
     const int n = (int)B->ids.size();
     if (n) hipLaunchKernelGGL(hb::kb_step_end, dim3((n + 127) / 128), dim3(128), 0, st, B->d_ctl, B->d_ids, n);
@@ -441,6 +454,16 @@ int hb_batch_create(const hb_create_opts *opts, size_t pool_bytes, int max_cases
         }
         B->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (B->fork) (void)hipEventDestroy(B->fork);
+        if (B->side) (void)hipStreamDestroy(B->side);
+        if (B->own_stream) (void)hipStreamDestroy(B->stream);
+        delete B;
+        return HB_EDEVICE;
+    }
     B->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     B->max_cases = max_cases;
     B->cases.assign(max_cases, nullptr);
@@ -462,6 +485,9 @@ int hb_batch_create(const hb_create_opts *opts, size_t pool_bytes, int max_cases
     if (rc != HB_OK) {
         if (B->d_cs) (void)hipFree(B->d_cs);
         B->pool.destroy();
+        (void)hipEventDestroy(B->fork);
+        (void)hipEventDestroy(B->join);
+        (void)hipStreamDestroy(B->side);
         if (B->own_stream) (void)hipStreamDestroy(B->stream);
         delete B;
         return rc;
@@ -481,6 +507,10 @@ void hb_batch_destroy(hb_batch_handle B)
     if (B->d_cs) (void)hipFree(B->d_cs);
     if (B->d_ctl) (void)hipFree(B->d_ctl);
     B->pool.destroy();
+    (void)hipStreamSynchronize(B->side);
+    (void)hipEventDestroy(B->fork);
+    (void)hipEventDestroy(B->join);
+    (void)hipStreamDestroy(B->side);
     if (B->own_stream) (void)hipStreamDestroy(B->stream);
     delete B;
 }
