@@ -174,6 +174,58 @@ def batch_converge(hb, hbcases, form, tol=1e-8, check_every=200, max_steps=60000
     return out
 
 
+def serving_plain(hb, hbcases, n=48, rate_per_s=None, cap_s=900.0, check_every=200, max_steps=60000, tol=1e-8):
+    """The serving workload served by the plain FP64 solver, one request at a
+    time in arrival order (first in, first out): the same requests and the
+    same arrival times in wall-clock time; each request is stepped until
+    R_rho <= tol (residual read every check_every steps); the run stops at
+    cap_s, cutting the request in progress off unconverged and leaving the
+    later ones unserved (listed, not dropped)."""
+    import numpy as np
+    reqs = hbcases.serving_requests(n)
+    arr = hbcases.poisson_arrivals(n, rate_per_s)
+    t0 = time.perf_counter()
+    rows = []
+    capped = False
+    for c, a in zip(reqs, arr):
+        row = {"name": c.name, "updates": c.updates, "arrival_s": float(a), "t_start_s": None, "t_done_s": None,
+               "status": "not served (wall cap)", "steps": 0, "R_rho": None}
+        rows.append(row)
+        if capped:
+            continue
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        if time.perf_counter() - t0 >= cap_s:
+            capped = True
+            continue
+        row["t_start_s"] = time.perf_counter() - t0
+        s = hb.Solver(c)
+        k, r = 0, float("inf")
+        while k < max_steps:
+            s.step(check_every)
+            k += check_every
+            r = s.residual()[0]
+            if r <= tol or time.perf_counter() - t0 >= cap_s:
+                break
+            if k % (10 * check_every) == 0:
+                log(f"plain fp64 serving {c.name}: {k} steps, R_rho {r:.2e}")
+        s.close()
+        row.update(t_done_s=time.perf_counter() - t0, steps=k, R_rho=r,
+                   status="converged" if r <= tol else "not converged (wall cap)")
+        capped = r > tol and time.perf_counter() - t0 >= cap_s
+        log(f"plain fp64 serving {c.name}: {row['status']}, {k} steps, latency {row['t_done_s'] - a:.1f} s")
+    wall = time.perf_counter() - t0
+    lat = np.array([r["t_done_s"] - r["arrival_s"] for r in rows if r["status"] == "converged"])
+    conv = int(len(lat))
+    return {"workload": f"serving_{n}_requests_seed260503480_arrivals260503481", "form": "plain fp64, one at a time",
+            "requests": n, "poisson_rate_per_s": rate_per_s, "cap_s": cap_s, "check_every": check_every,
+            "wall_s": wall, "converged": conv, "cases_per_h": 3600.0 * conv / wall,
+            "p50_time_to_converged_s": float(np.percentile(lat, 50)) if conv else None,
+            "p99_time_to_converged_s": float(np.percentile(lat, 99)) if conv else None,
+            "requests_detail": rows}
+
+
 def serving(hb, hbcases, n=48, rate_per_s=None, cap_s=900.0, check_every=200, max_steps=60000, tol=1e-8):
     """The serving workload: n seeded requests drawn as the batched sweep with
     1/16 outliers of 128^2 cells x 64^2 velocities x N_H = 5, arriving as a
@@ -404,7 +456,7 @@ def main():
                     help="run only the batched sweep's step time, the sweep to convergence, the serving "
                          "measurement or the HB-vs-time-domain comparison (prints its JSON)")
     ap.add_argument("--form", choices=("batched", "plain"), default="batched",
-                    help="batch_converge: all cases batched (mixed) or one at a time (FP64)")
+                    help="batch_converge / serving: all cases batched (mixed) or one at a time (FP64)")
     ap.add_argument("--first", type=int, default=0, help="batch_converge plain: first case")
     ap.add_argument("--count", type=int, default=64, help="batch_converge plain: number of cases")
     ap.add_argument("--cap", type=float, default=900.0, help="batch_converge / serving: wall-clock cap (s)")
@@ -466,7 +518,8 @@ def main():
         return
     if args.only == "serving":
         rate = args.rate if args.rate is not None else 0.8 * BATCHED_CAPACITY_PER_H / 3600.0
-        print(json.dumps(serving(hb, hbcases, n=args.requests, rate_per_s=rate, cap_s=args.cap)), flush=True)
+        fn = serving if args.form == "batched" else serving_plain
+        print(json.dumps(fn(hb, hbcases, n=args.requests, rate_per_s=rate, cap_s=args.cap)), flush=True)
         return
 
     prec = hb.HB_MIXED if args.precision == "mixed" else hb.HB_FP64
