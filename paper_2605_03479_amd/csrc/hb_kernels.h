@@ -1034,11 +1034,14 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
     const double kh = P.K - 5.0, kb = P.K - 3.0, dgw = dG * P.omega;
 #pragma unroll
     for (int n = 0; n < NT; n++) {
+        // E of Eq. (17) is circulant with a zero diagonal: E_nm = e_d for
+        // d = (n - m) mod N_T, e_d = E_d0
         double Eh = 0.0, Eb = 0.0;
 #pragma unroll
-        for (int m = 0; m < NT; m++) {
-            Eh += P.E[n * NT + m] * hk[m];
-            Eb += P.E[n * NT + m] * bk[m];
+        for (int d = 1; d < NT; d++) {
+            const int m = (n - d + NT) % NT;
+            Eh = fma(P.E[d * NT], hk[m], Eh);
+            Eb = fma(P.E[d * NT], bk[m], Eb);
         }
         const gptr<const double> cc = cr + n * CREC;
         const double *ct = ctab + n * 4 * M;

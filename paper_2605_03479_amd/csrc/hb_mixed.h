@@ -131,11 +131,15 @@ __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float 
     cfloat *ls = wave_uniform_f(P.lscale32);
 #pragma unroll
     for (int n = 0; n < NT; n++) {
+        // E of Eq. (17) is circulant with a zero diagonal: E_nm = e_d for
+        // d = (n - m) mod N_T, e_d = E_d0, so the sum takes N_T - 1 wave-uniform
+        // coefficients
         float Eh = 0.0f, Eb = 0.0f;
 #pragma unroll
-        for (int mm = 0; mm < NT; mm++) {
-            Eh = fmaf(P.Ef[n * NT + mm], hk[mm], Eh);
-            Eb = fmaf(P.Ef[n * NT + mm], bk[mm], Eb);
+        for (int d = 1; d < NT; d++) {
+            const int mm = (n - d + NT) % NT;
+            Eh = fmaf(P.Ef[d * NT], hk[mm], Eh);
+            Eb = fmaf(P.Ef[d * NT], bk[mm], Eb);
         }
         cfloat *q = cc + n * CREC32;
         const float *ct = ctab + n * 4 * M;
