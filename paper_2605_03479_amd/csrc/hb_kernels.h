@@ -1116,66 +1116,20 @@ __device__ inline void update_int_cell_d(const Params &P, const TS *__restrict__
         const double rUm = rcx[iU], rUp = rcx[iU + 1], rVm = rcy[jV], rVp = rcy[jV + 1];
         double hk[NT], bk[NT], dh[NT], db[NT];
         const long e0 = (long)c * NT * P.ls + ap;
-        // Mixed form with five or more levels: the next level's 22 (32-bit)
-        // stencil words are loaded before this level's arithmetic, hiding one
-        // memory round trip per level at no cost in occupancy.  With fewer
-        // levels, or FP64 words, the extra registers cost a wave per SIMD.
-        constexpr bool PIPE = sizeof(TS) == 4 && NT >= 5;
-        struct Lv {
-            TS hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
-        };
-        auto ld_level = [&](int n) {
-            Lv L;
-            const gptr<const TS> hp = G(h + e0 + (long)n * P.ls), bp = G(b + e0 + (long)n * P.ls);
-            L.hc = hp[0];
-            L.bc = bp[0];
-            L.hW = hp[-sx];
-            L.bW = bp[-sx];
-            L.hE = hp[sx];
-            L.bE = bp[sx];
-            L.hS = hp[-sy];
-            L.bS = bp[-sy];
-            L.hN = hp[sy];
-            L.bN = bp[sy];
-            L.hUF = hp[2 * oU];
-            L.bUF = bp[2 * oU];
-            L.hUs = hp[oU - sy];
-            L.bUs = bp[oU - sy];
-            L.hUn = hp[oU + sy];
-            L.bUn = bp[oU + sy];
-            L.hVF = hp[2 * oV];
-            L.bVF = bp[2 * oV];
-            L.hVw = hp[oV - sx];
-            L.bVw = bp[oV - sx];
-            L.hVe = hp[oV + sx];
-            L.bVe = bp[oV + sx];
-            return L;
-        };
-        Lv nxt{};
-        if constexpr (PIPE) nxt = ld_level(0);
 #pragma unroll
         for (int n = 0; n < NT; n++) {
             double hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
-            if constexpr (PIPE) {
-                const Lv L = nxt;
-                if (n + 1 < NT) nxt = ld_level(n + 1);
-                hc = L.hc + rh, bc = L.bc + rb, hW = L.hW + rh, bW = L.bW + rb, hE = L.hE + rh, bE = L.bE + rb;
-                hS = L.hS + rh, bS = L.bS + rb, hN = L.hN + rh, bN = L.bN + rb;
-                hUF = L.hUF + rh, bUF = L.bUF + rb, hUs = L.hUs + rh, bUs = L.bUs + rb, hUn = L.hUn + rh, bUn = L.bUn + rb;
-                hVF = L.hVF + rh, bVF = L.bVF + rb, hVw = L.hVw + rh, bVw = L.bVw + rb, hVe = L.hVe + rh, bVe = L.bVe + rb;
-            } else {
-                const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
-                hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
-                hW = ldv<TS>(hp, -sx, rh), bW = ldv<TS>(bp, -sx, rb), hE = ldv<TS>(hp, sx, rh), bE = ldv<TS>(bp, sx, rb);
-                hS = ldv<TS>(hp, -sy, rh), bS = ldv<TS>(bp, -sy, rb), hN = ldv<TS>(hp, sy, rh), bN = ldv<TS>(bp, sy, rb);
-                // upwind x-neighbour: far value and diagonals; upwind y-neighbour likewise
-                const TS *hq = hp + oU, *bq = bp + oU;
-                hUF = ldv<TS>(hq, oU, rh), bUF = ldv<TS>(bq, oU, rb), hUs = ldv<TS>(hq, -sy, rh), bUs = ldv<TS>(bq, -sy, rb);
-                hUn = ldv<TS>(hq, sy, rh), bUn = ldv<TS>(bq, sy, rb);
-                const TS *hr = hp + oV, *br = bp + oV;
-                hVF = ldv<TS>(hr, oV, rh), bVF = ldv<TS>(br, oV, rb), hVw = ldv<TS>(hr, -sx, rh), bVw = ldv<TS>(br, -sx, rb);
-                hVe = ldv<TS>(hr, sx, rh), bVe = ldv<TS>(br, sx, rb);
-            }
+            const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
+            hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
+            hW = ldv<TS>(hp, -sx, rh), bW = ldv<TS>(bp, -sx, rb), hE = ldv<TS>(hp, sx, rh), bE = ldv<TS>(bp, sx, rb);
+            hS = ldv<TS>(hp, -sy, rh), bS = ldv<TS>(bp, -sy, rb), hN = ldv<TS>(hp, sy, rh), bN = ldv<TS>(bp, sy, rb);
+            // upwind x-neighbour: far value and diagonals; upwind y-neighbour likewise
+            const TS *hq = hp + oU, *bq = bp + oU;
+            hUF = ldv<TS>(hq, oU, rh), bUF = ldv<TS>(bq, oU, rb), hUs = ldv<TS>(hq, -sy, rh), bUs = ldv<TS>(bq, -sy, rb);
+            hUn = ldv<TS>(hq, sy, rh), bUn = ldv<TS>(bq, sy, rb);
+            const TS *hr = hp + oV, *br = bp + oV;
+            hVF = ldv<TS>(hr, oV, rh), bVF = ldv<TS>(br, oV, rb), hVw = ldv<TS>(hr, -sx, rh), bVw = ldv<TS>(br, -sx, rb);
+            hVe = ldv<TS>(hr, sx, rh), bVe = ldv<TS>(br, sx, rb);
             hk[n] = hc;
             bk[n] = bc;
             const double sxh = vanleer_fast((hc - hW) * rxm, (hE - hc) * rxp);
@@ -1278,41 +1232,6 @@ __device__ inline void update_bnd_cell_d(const Params &P, const TS *__restrict__
         const double rUm = G(P.rcx)[iUc], rUp = G(P.rcx)[iUc + 1], rVm = G(P.rcy)[jVc], rVp = G(P.rcy)[jVc + 1];
         double hk[NT], bk[NT], dh[NT], db[NT];
         const long e0 = (long)c * NT * P.ls + ap;
-        // as in the interior update: level-ahead loads in the mixed form with
-        // five or more levels
-        constexpr bool PIPE = sizeof(TS) == 4 && NT >= 5;
-        struct Lv {
-            TS hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
-        };
-        auto ld_level = [&](int n) {
-            Lv L;
-            const gptr<const TS> hp = G(h + e0 + (long)n * P.ls), bp = G(b + e0 + (long)n * P.ls);
-            L.hc = hp[0];
-            L.bc = bp[0];
-            L.hW = hp[oW];
-            L.bW = bp[oW];
-            L.hE = hp[oE];
-            L.bE = bp[oE];
-            L.hS = hp[oS];
-            L.bS = bp[oS];
-            L.hN = hp[oN];
-            L.bN = bp[oN];
-            L.hUF = hp[oUc + oUF];
-            L.bUF = bp[oUc + oUF];
-            L.hUs = hp[oUc + oS];
-            L.bUs = bp[oUc + oS];
-            L.hUn = hp[oUc + oN];
-            L.bUn = bp[oUc + oN];
-            L.hVF = hp[oVc + oVF];
-            L.bVF = bp[oVc + oVF];
-            L.hVw = hp[oVc + oW];
-            L.bVw = bp[oVc + oW];
-            L.hVe = hp[oVc + oE];
-            L.bVe = bp[oVc + oE];
-            return L;
-        };
-        Lv nxt{};
-        if constexpr (PIPE) nxt = ld_level(0);
         // the level loop unrolled up to three levels (the compiler can then
         // interleave one level's record loads and tables with the previous
         // level's arithmetic), kept rolled above for code size
@@ -1320,28 +1239,19 @@ __device__ inline void update_bnd_cell_d(const Params &P, const TS *__restrict__
 #pragma unroll UNR
         for (int n = 0; n < NT; n++) {
             double hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
-            if constexpr (PIPE) {
-                const Lv L = nxt;
-                if (n + 1 < NT) nxt = ld_level(n + 1);
-                hc = L.hc + rh, bc = L.bc + rb, hW = L.hW + rh, bW = L.bW + rb, hE = L.hE + rh, bE = L.bE + rb;
-                hS = L.hS + rh, bS = L.bS + rb, hN = L.hN + rh, bN = L.bN + rb;
-                hUF = L.hUF + rh, bUF = L.bUF + rb, hUs = L.hUs + rh, bUs = L.bUs + rb, hUn = L.hUn + rh, bUn = L.bUn + rb;
-                hVF = L.hVF + rh, bVF = L.bVF + rb, hVw = L.hVw + rh, bVw = L.bVw + rb, hVe = L.hVe + rh, bVe = L.bVe + rb;
-            } else {
-                const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
-                hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
-                hW = ldv<TS>(hp, oW, rh), bW = ldv<TS>(bp, oW, rb);
-                hE = ldv<TS>(hp, oE, rh), bE = ldv<TS>(bp, oE, rb);
-                hS = ldv<TS>(hp, oS, rh), bS = ldv<TS>(bp, oS, rb);
-                hN = ldv<TS>(hp, oN, rh), bN = ldv<TS>(bp, oN, rb);
-                const TS *hq = hp + oUc, *bq = bp + oUc, *hr = hp + oVc, *br = bp + oVc;
-                hUF = ldv<TS>(hq, oUF, rh), bUF = ldv<TS>(bq, oUF, rb);
-                hUs = ldv<TS>(hq, oS, rh), bUs = ldv<TS>(bq, oS, rb);
-                hUn = ldv<TS>(hq, oN, rh), bUn = ldv<TS>(bq, oN, rb);
-                hVF = ldv<TS>(hr, oVF, rh), bVF = ldv<TS>(br, oVF, rb);
-                hVw = ldv<TS>(hr, oW, rh), bVw = ldv<TS>(br, oW, rb);
-                hVe = ldv<TS>(hr, oE, rh), bVe = ldv<TS>(br, oE, rb);
-            }
+            const TS *hp = h + e0 + (long)n * P.ls, *bp = b + e0 + (long)n * P.ls;
+            hc = ldv<TS>(hp, 0, rh), bc = ldv<TS>(bp, 0, rb);
+            hW = ldv<TS>(hp, oW, rh), bW = ldv<TS>(bp, oW, rb);
+            hE = ldv<TS>(hp, oE, rh), bE = ldv<TS>(bp, oE, rb);
+            hS = ldv<TS>(hp, oS, rh), bS = ldv<TS>(bp, oS, rb);
+            hN = ldv<TS>(hp, oN, rh), bN = ldv<TS>(bp, oN, rb);
+            const TS *hq = hp + oUc, *bq = bp + oUc, *hr = hp + oVc, *br = bp + oVc;
+            hUF = ldv<TS>(hq, oUF, rh), bUF = ldv<TS>(bq, oUF, rb);
+            hUs = ldv<TS>(hq, oS, rh), bUs = ldv<TS>(bq, oS, rb);
+            hUn = ldv<TS>(hq, oN, rh), bUn = ldv<TS>(bq, oN, rb);
+            hVF = ldv<TS>(hr, oVF, rh), bVF = ldv<TS>(br, oVF, rb);
+            hVw = ldv<TS>(hr, oW, rh), bVw = ldv<TS>(br, oW, rb);
+            hVe = ldv<TS>(hr, oE, rh), bVe = ldv<TS>(br, oE, rb);
             hk[n] = hc;
             bk[n] = bc;
             const double sxh = slope_c(hW, hc, hE, mx, rxm, rxp), sxb = slope_c(bW, bc, bE, mx, rxm, rxp);
