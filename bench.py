@@ -38,17 +38,17 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "39b4de510ee348cd",
+    "sources_sha256_16": "c4560ae1d41d6a9c",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 264749773,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 616719974,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73697997,
-        "shear64_v32_nh1_kn1_st1/mixed/moments": 152960102,
-        "shear64_v32_nh1_kn1_st1/mixed/update_int": 249659290,
-        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38384742,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1079329280,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2222422323,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 273405645,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 263704883,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 616566170,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73660928,
+        "shear64_v32_nh1_kn1_st1/mixed/moments": 152952627,
+        "shear64_v32_nh1_kn1_st1/mixed/update_int": 249618534,
+        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38385562,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1084925030,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2223754752,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 272785715,
     },
 }
 
