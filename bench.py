@@ -4,14 +4,15 @@ One step = one pass of the whole pseudo step (moments, faces, cells,
 local steps + residual, interior and boundary-ring update) over the
 64 x 64-cell, 48 x 48-velocity (on [-5, 5]), N_H = 4 (nine levels) thermal
 cavity (Kn = 1, St = 1, bottom wall T0 (1 + 0.5 sin wt), Shakhov) in the
-mixed form (FP32 storage of the deviation from the rest Maxwellian, FP64
-moments, W and residual), state resident in HBM.  value = cell x velocity
-x level updates per second.
+mixed form (FP32 storage of the deviation from the rest Maxwellian and FP32
+per-velocity arithmetic; FP64 moment sums, W and residual), state resident in
+HBM.  value = cell x velocity x level updates per second.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                   [--precision fp64|mixed] [--workload thermal|shear] [--no-extra] [--copy-mib N]
-                  [--only batch|batch_converge|serving|hbtd] [--td-cap S]
+                  [--only batch|batch_converge|serving|hbtd] [--form batched|plain]
+                  [--first I] [--count N] [--cap S] [--requests N] [--rate R] [--td-cap S]
 Besides the headline, the JSON line carries: the headline case's one-step
 error against the FP64 oracle at full size, the oracle timed on the host
 (all threads and one), the time to converge from rest, the 64 x 64-cell,
