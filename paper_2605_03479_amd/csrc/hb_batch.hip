@@ -187,8 +187,8 @@ struct hb_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // the boundary-ring updates run beside the interior updates on this
-    // stream (default priority), forked and joined per cache group
+    // the second stream of a batch step (default priority): every other cache
+    // group runs on it, forked from and joined to `stream` once per step
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     int num_cu = 256;
@@ -352,38 +352,46 @@ static void launch_moments(const CacheGroup &cg, int pm, const CaseDev *cs, cons
         hipLaunchKernelGGL(hb::kb_moments<float>, dim3(L.grid), dim3(256), 0, st, cs, ctl, L.d_items, L.d_bstart);
 }
 
+// One cache group's phases of a step, on one stream.
+static void enqueue_group(const CacheGroup &cg, const CaseDev *cs, const CaseCtl *ctl, hipStream_t st)
+{
+    launch_moments(cg, 0, cs, ctl, st);
+    launch_moments(cg, 1, cs, ctl, st);
+    if (cg.faces.grid)
+        hipLaunchKernelGGL(hb::kb_faces, dim3(cg.faces.grid), dim3(128), 0, st, cs, ctl, cg.faces.d_items,
+                           cg.faces.d_bstart);
+    if (cg.cells.grid)
+        hipLaunchKernelGGL(hb::kb_cells, dim3(cg.cells.grid), dim3(128), 0, st, cs, ctl, cg.cells.d_items,
+                           cg.cells.d_bstart);
+    if (cg.dts.grid)
+        hipLaunchKernelGGL(hb::kb_dt, dim3(cg.dts.grid), dim3(128), 0, st, cs, ctl, cg.dts.d_items,
+                           cg.dts.d_bstart);
+    if (cg.resid.grid)
+        hipLaunchKernelGGL(hb::kb_resid, dim3(cg.resid.grid), dim3(256), 0, st, cs, ctl, cg.resid.d_items,
+                           cg.resid.d_bstart);
+    for (auto &g : cg.groups) launch_group(g, cs, ctl, st);
+}
+
 // The launches of one batch step: per cache group, the phases in the order
-// of the single-case step; then the buffer swap of every stepped case.
+// of the single-case step; then the buffer swap of every stepped case.  The
+// cache groups hold disjoint cases, so they run on two streams, alternating:
+// one group's latency-bound phases (faces, cells, local steps, residual) and
+// ring update then overlap the other's moments and interior update.
 static void enqueue_step(hb_batch *B)
 {
     hipStream_t st = B->stream;
     const CaseDev *cs = B->d_cs;
     const CaseCtl *ctl = B->d_ctl;
-    for (const CacheGroup &cg : B->cgs) {
-        launch_moments(cg, 0, cs, ctl, st);
-        launch_moments(cg, 1, cs, ctl, st);
-        if (cg.faces.grid)
-            hipLaunchKernelGGL(hb::kb_faces, dim3(cg.faces.grid), dim3(128), 0, st, cs, ctl, cg.faces.d_items,
-                               cg.faces.d_bstart);
-        if (cg.cells.grid)
-            hipLaunchKernelGGL(hb::kb_cells, dim3(cg.cells.grid), dim3(128), 0, st, cs, ctl, cg.cells.d_items,
-                               cg.cells.d_bstart);
-        if (cg.dts.grid)
-            hipLaunchKernelGGL(hb::kb_dt, dim3(cg.dts.grid), dim3(128), 0, st, cs, ctl, cg.dts.d_items,
-                               cg.dts.d_bstart);
-        if (cg.resid.grid)
-            hipLaunchKernelGGL(hb::kb_resid, dim3(cg.resid.grid), dim3(256), 0, st, cs, ctl, cg.resid.d_items,
-                               cg.resid.d_bstart);
-        if (B->side) {
-            (void)hipEventRecord(B->fork, st);
-            (void)hipStreamWaitEvent(B->side, B->fork, 0);
-            for (auto &g : cg.groups) launch_group(g, cs, ctl, B->side, false, true);
-            for (auto &g : cg.groups) launch_group(g, cs, ctl, st, true, false);
-            (void)hipEventRecord(B->join, B->side);
-            (void)hipStreamWaitEvent(st, B->join, 0);
-        } else {
-            for (auto &g : cg.groups) launch_group(g, cs, ctl, st);
-        }
+    const bool two = B->side && B->cgs.size() > 1;
+    if (two) {
+        (void)hipEventRecord(B->fork, st);
+        (void)hipStreamWaitEvent(B->side, B->fork, 0);
+    }
+    for (size_t k = 0; k < B->cgs.size(); k++)
+        enqueue_group(B->cgs[k], cs, ctl, two && (k & 1) ? B->side : st);
+    if (two) {
+        (void)hipEventRecord(B->join, B->side);
+        (void)hipStreamWaitEvent(st, B->join, 0);
     }
     const int n = (int)B->ids.size();
     if (n) hipLaunchKernelGGL(hb::kb_step_end, dim3((n + 127) / 128), dim3(128), 0, st, B->d_ctl, B->d_ids, n);
