@@ -183,13 +183,17 @@ struct CacheGroup {
 
 }  // namespace
 
+// streams a batch step spreads its cache groups over
+#define HB_BATCH_LANES 4
+
 struct hb_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // the second stream of a batch step (default priority): every other cache
-    // group runs on it, forked from and joined to `stream` once per step
-    hipStream_t side = nullptr;
+    // the further streams of a batch step (default priority): cache group k
+    // runs on lane k % HB_BATCH_LANES (lane 0 is `stream`), the lanes forked
+    // from and joined to `stream` once per step
+    hipStream_t side[HB_BATCH_LANES - 1]{};
     hipEvent_t fork = nullptr, join = nullptr;
     int num_cu = 256;
     HbPool pool;
@@ -374,23 +378,26 @@ static void enqueue_group(const CacheGroup &cg, const CaseDev *cs, const CaseCtl
 
 // The launches of one batch step: per cache group, the phases in the order
 // of the single-case step; then the buffer swap of every stepped case.  The
-// cache groups hold disjoint cases, so they run on two streams, alternating:
-// one group's latency-bound phases (faces, cells, local steps, residual) and
-// ring update then overlap the other's moments and interior update.
+// cache groups hold disjoint cases, so they run on HB_BATCH_LANES streams in
+// turn: one group's latency-bound phases (faces, cells, local steps,
+// residual) and ring update then overlap another's moments and interior
+// update.
 static void enqueue_step(hb_batch *B)
 {
     hipStream_t st = B->stream;
     const CaseDev *cs = B->d_cs;
     const CaseCtl *ctl = B->d_ctl;
-    const bool two = B->side && B->cgs.size() > 1;
-    if (two) {
+    const int lanes = (int)std::min<size_t>(HB_BATCH_LANES, B->cgs.size());
+    if (lanes > 1) {
         (void)hipEventRecord(B->fork, st);
-        (void)hipStreamWaitEvent(B->side, B->fork, 0);
+        for (int l = 1; l < lanes; l++) (void)hipStreamWaitEvent(B->side[l - 1], B->fork, 0);
     }
-    for (size_t k = 0; k < B->cgs.size(); k++)
-        enqueue_group(B->cgs[k], cs, ctl, two && (k & 1) ? B->side : st);
-    if (two) {
-        (void)hipEventRecord(B->join, B->side);
+    for (size_t k = 0; k < B->cgs.size(); k++) {
+        const int l = (int)(k % HB_BATCH_LANES);
+        enqueue_group(B->cgs[k], cs, ctl, l == 0 ? st : B->side[l - 1]);
+    }
+    for (int l = 1; l < lanes; l++) {
+        (void)hipEventRecord(B->join, B->side[l - 1]);
         (void)hipStreamWaitEvent(st, B->join, 0);
     }
     const int n = (int)B->ids.size();
@@ -462,12 +469,16 @@ int hb_batch_create(const hb_create_opts *opts, size_t pool_bytes, int max_cases
         }
         B->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&B->join, hipEventDisableTiming) == hipSuccess;
+    for (int l = 0; ok && l < HB_BATCH_LANES - 1; l++)
+        ok = hipStreamCreateWithFlags(&B->side[l], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         if (B->fork) (void)hipEventDestroy(B->fork);
-        if (B->side) (void)hipStreamDestroy(B->side);
+        if (B->join) (void)hipEventDestroy(B->join);
+        for (auto &sd : B->side)
+            if (sd) (void)hipStreamDestroy(sd);
         if (B->own_stream) (void)hipStreamDestroy(B->stream);
         delete B;
         return HB_EDEVICE;
@@ -495,7 +506,7 @@ int hb_batch_create(const hb_create_opts *opts, size_t pool_bytes, int max_cases
         B->pool.destroy();
         (void)hipEventDestroy(B->fork);
         (void)hipEventDestroy(B->join);
-        (void)hipStreamDestroy(B->side);
+        for (auto &sd : B->side) (void)hipStreamDestroy(sd);
         if (B->own_stream) (void)hipStreamDestroy(B->stream);
         delete B;
         return rc;
@@ -515,10 +526,12 @@ void hb_batch_destroy(hb_batch_handle B)
     if (B->d_cs) (void)hipFree(B->d_cs);
     if (B->d_ctl) (void)hipFree(B->d_ctl);
     B->pool.destroy();
-    (void)hipStreamSynchronize(B->side);
+    for (auto &sd : B->side) {
+        (void)hipStreamSynchronize(sd);
+        (void)hipStreamDestroy(sd);
+    }
     (void)hipEventDestroy(B->fork);
     (void)hipEventDestroy(B->join);
-    (void)hipStreamDestroy(B->side);
     if (B->own_stream) (void)hipStreamDestroy(B->stream);
     delete B;
 }
