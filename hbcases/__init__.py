@@ -61,6 +61,8 @@ class Case:
     dt_mode: int = 0          # 0 = local pseudo step (Eqs. 31-32); 1 = global step dt_fixed
     dt_fixed: float = 0.0
     vrule: int = 0            # 1-D velocity rule: 0 = trapezoid on [-umax, umax], 1 = Gauss-Hermite
+    Mv: int = 0               # nodes along v; 0 = M (square grid)
+    vmax: float = 0.0         # trapezoid range along v; 0 = umax
     name: str = field(default="", compare=False)
 
     @property
@@ -72,8 +74,18 @@ class Case:
         return self.nx * self.ny
 
     @property
+    def Mv_(self):
+        """Nodes along v."""
+        return self.Mv or self.M
+
+    @property
+    def vmax_(self):
+        """Trapezoid range along v."""
+        return self.vmax if self.vmax > 0.0 else self.umax
+
+    @property
     def nv(self):
-        return self.M * self.M
+        return self.M * self.Mv_
 
     @property
     def updates(self):

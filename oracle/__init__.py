@@ -42,7 +42,8 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_double, _D, _D, ctypes.c_int]
+                                  ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  _D, _D]
         L.hbref_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.hbref_td_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
         L.hbref_residual.argtypes = [ctypes.c_void_p, _D]
@@ -147,10 +148,20 @@ def gauss_hermite(M):
 
 
 def velocity_rule(case):
-    """1-D nodes and weights of a case's velocity rule."""
+    """1-D nodes and weights of a case's velocity rule along u."""
     if getattr(case, "vrule", 0) == 1:
         return gauss_hermite(case.M)
     return velocity_grid(case.M, case.umax)
+
+
+def velocity_rule_v(case):
+    """1-D nodes and weights of a case's velocity rule along v (M_v nodes; the
+    trapezoid on [-vmax, vmax])."""
+    Mv = getattr(case, "Mv", 0) or case.M
+    if getattr(case, "vrule", 0) == 1:
+        return gauss_hermite(Mv)
+    vmax = getattr(case, "vmax", 0.0)
+    return velocity_grid(Mv, vmax if vmax > 0.0 else case.umax)
 
 
 # ---------------------------------------------------------------- solver
@@ -166,11 +177,14 @@ class Oracle:
         NH = 0 if td else case.NH
         dt_mode = 1 if td else case.dt_mode
         u1, w1 = velocity_rule(case) if getattr(case, "vrule", 0) else (None, None)
+        Mv = getattr(case, "Mv", 0) or case.M
+        vmax = getattr(case, "vmax", 0.0)
+        v1, w1v = velocity_rule_v(case) if getattr(case, "vrule", 0) else (None, None)
         rc = lib().hbref_setup(self._h, case.nx, case.ny, case.L, case.H, _p(xf), _p(yf), case.M,
                                case.umax, case.Kn, case.St, NH, _p(walls), case.cfl,
                                case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K,
                                case.macro_mode, dt_mode, case.dt_fixed, _p(u1), _p(w1),
-                               int(getattr(case, "level_mass", 1)))
+                               int(getattr(case, "level_mass", 1)), Mv, float(vmax), _p(v1), _p(w1v))
         if rc != 0:
             lib().hbref_free(self._h)
             self._h = None

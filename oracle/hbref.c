@@ -38,10 +38,11 @@ typedef struct {
     /* geometry */
     int nx, ny, nc;
     double *xf, *yf, *xc, *yc, *dx, *dy;
-    /* velocity grid (tensor product of a 1-D closed trapezoid rule) */
-    int M, nv;
-    double umax;
-    double *u1, *w1;
+    /* velocity grid: tensor product of a 1-D rule of M nodes along u and one
+     * of Mv nodes along v */
+    int M, Mv, nv;
+    double umax, vmax;
+    double *u1, *w1, *v1, *w1v;
     double *u, *v, *w;
     /* physics and numerics */
     int NH, NT, K;
@@ -402,7 +403,7 @@ void *hbref_new(void) { return calloc(1, sizeof(hbref)); }
 static void free_arrays(hbref *o)
 {
     double **ptrs[] = {&o->xf,  &o->yf,  &o->xc,  &o->yc,  &o->dx,   &o->dy,   &o->u1, &o->w1,
-                       &o->u,   &o->v,   &o->w,   &o->W,   &o->h,    &o->b,    &o->Wn, &o->dtc,
+                       &o->v1,  &o->w1v, &o->u,   &o->v,   &o->w,   &o->W,   &o->h,    &o->b,    &o->Wn, &o->dtc,
                        &o->divH, &o->divB, &o->divF, &o->q, &o->sxh, &o->syh, &o->sxb, &o->syb,
                        &o->Fx,  &o->Fy};
     for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); k++) {
@@ -432,21 +433,34 @@ static void wall_state_at(const hbref *o, int wl, double theta, double *ut, doub
  * wall-tangential velocity along +x (bottom/top) or +y (left/right), T in T0.
  * dt_mode 0: local pseudo step of Eqs. (31)-(32); 1: one global step dt_fixed.
  * u1in, w1in: NULL for the closed trapezoid rule on [-umax, umax], else M
- * increasing 1-D nodes and their weights (umax is then the last node). */
+ * increasing 1-D nodes and their weights (umax is then the last node).
+ * Mv, vmax, v1in, w1vin: the same for the v axis (Mv = 0 takes M and the u
+ * rule, vmax <= 0 takes umax). */
 int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, const double *yf, int M,
                 double umax, double Kn, double St, int NH, const double *walls, double cfl, int face_dt,
                 double Pr, double omega_vss, double alpha_vss, int K, int macro_mode, int dt_mode,
-                double dt_fixed, const double *u1in, const double *w1in, int level_mass)
+                double dt_fixed, const double *u1in, const double *w1in, int level_mass, int Mv, double vmax,
+                const double *v1in, const double *w1vin)
 {
     hbref *o = (hbref *)p;
-    if (nx < 3 || ny < 3 || M < 2 || (M % 2) != 0 || NH < 0 || 2 * NH + 1 > NTMAX || Kn <= 0.0) return -1;
+    if (Mv == 0) {
+        Mv = M;
+        v1in = u1in;
+        w1vin = w1in;
+    }
+    if (!(vmax > 0.0)) vmax = umax;
+    if (nx < 3 || ny < 3 || M < 2 || (M % 2) != 0 || Mv < 2 || (Mv % 2) != 0 || NH < 0 || 2 * NH + 1 > NTMAX ||
+        Kn <= 0.0)
+        return -1;
     free_arrays(o);
     o->nx = nx;
     o->ny = ny;
     o->nc = nx * ny;
     o->M = M;
-    o->nv = M * M;
+    o->Mv = Mv;
+    o->nv = M * Mv;
     o->umax = umax;
+    o->vmax = vmax;
     o->NH = NH;
     o->NT = 2 * NH + 1;
     o->K = K;
@@ -492,16 +506,25 @@ int hbref_setup(void *p, int nx, int ny, double L, double Hh, const double *xf, 
     } else {
         hbref_velocity_grid(M, umax, o->u1, o->w1);
     }
+    o->v1 = malloc(sizeof(double) * Mv);
+    o->w1v = malloc(sizeof(double) * Mv);
+    if (v1in && w1vin) {
+        memcpy(o->v1, v1in, sizeof(double) * Mv);
+        memcpy(o->w1v, w1vin, sizeof(double) * Mv);
+        o->vmax = v1in[Mv - 1];
+    } else {
+        hbref_velocity_grid(Mv, vmax, o->v1, o->w1v);
+    }
     int nv = o->nv;
     o->u = malloc(sizeof(double) * nv);
     o->v = malloc(sizeof(double) * nv);
     o->w = malloc(sizeof(double) * nv);
-    for (int iv = 0; iv < M; iv++)
+    for (int iv = 0; iv < Mv; iv++)
         for (int iu = 0; iu < M; iu++) {
             int a = iv * M + iu;
             o->u[a] = o->u1[iu];
-            o->v[a] = o->u1[iv];
-            o->w[a] = o->w1[iu] * o->w1[iv];
+            o->v[a] = o->v1[iv];
+            o->w[a] = o->w1[iu] * o->w1v[iv];
         }
 
     hbref_E(o->NT, o->E);
@@ -568,7 +591,7 @@ static double local_dt(const hbref *o, int c)
         prim_of(o->K, o->W + IDX(c, n) * 4, p);
         double cs = sqrt(o->gamma / (2.0 * p[3]));
         double ut = fmax(o->umax, fabs(p[1])) + cs;
-        double vt = fmax(o->umax, fabs(p[2])) + cs;
+        double vt = fmax(o->vmax, fabs(p[2])) + cs;
         double nc = (o->dy[j] * ut + o->dx[i] * vt) / (o->dx[i] * o->dy[j]);
         if (nc > nu) nu = nc;
     }

@@ -117,6 +117,58 @@ def test_transpose_symmetry(oracle_mod):
     np.testing.assert_allclose(Wb, Wat, atol=1e-12 * scale)
 
 
+def _transposed(c):
+    """The case with x and y swapped: walls (bottom, right, top, left) become
+    (left, top, right, bottom), each keeping its tangential velocity (along +x
+    on bottom/top, +y on left/right), and the two velocity axes swap."""
+    w = c.walls
+    return c.with_(nx=c.ny, ny=c.nx, L=c.H, H=c.L, M=c.Mv_, Mv=c.M, umax=c.vmax_, vmax=c.umax,
+                   walls=(w[3], w[2], w[1], w[0]))
+
+
+def test_transpose_symmetry_rectangular_velocity_grid(oracle_mod):
+    """Rectangular cells, a rectangular velocity grid (10 nodes on [-4, 4]
+    along u, 14 on [-5, 5] along v), a sliding lid and a heated wall: swapping
+    x and y (and u and v) maps the state onto itself transposed, which fixes
+    which axis of the grid each face, slope and CFL bound takes."""
+    w = [list(r) for r in hbcases.lid_walls(0.06)]
+    w[0][4] = 0.15
+    a = Case(7, 5, 10, 4.0, 0.4, 1.5, 1, tuple(map(tuple, w)), L=1.4, H=1.0, Mv=14, vmax=5.0)
+    b = _transposed(a)
+    oa, ob = oracle_mod.Oracle(a), oracle_mod.Oracle(b)
+    assert oa.nv == ob.nv == 140
+    oa.step(30)
+    ob.step(30)
+    Wa, ha, _ = oa.state()
+    Wb, hb, _ = ob.state()
+    Wa = Wa.reshape(a.ny, a.nx, a.NT, 4)
+    Wb = Wb.reshape(b.ny, b.nx, b.NT, 4)
+    scale = np.abs(Wa[..., 1]).max()
+    assert scale > 1e-4
+    np.testing.assert_allclose(Wb, np.transpose(Wa, (1, 0, 2, 3))[..., [0, 2, 1, 3]], atol=1e-12 * scale)
+    Ha = ha.reshape(a.ny, a.nx, a.NT, a.Mv_, a.M)  # [j, i, n, iv, iu]
+    Hb = hb.reshape(b.ny, b.nx, b.NT, b.Mv_, b.M)
+    np.testing.assert_allclose(Hb, np.transpose(Ha, (1, 0, 2, 4, 3)), atol=1e-12 * np.abs(Ha).max())
+
+
+def test_rectangular_grid_layout_and_rest_state(oracle_mod):
+    """On a rectangular grid (28 nodes on [-7, 7] along u, 30 on [-7.5, 7.5]
+    along v) the initial state is the rest Maxwellian exp(-u^2 - v^2)/pi at
+    a = iv*M + iu, and it stays a fixed point (Sec. 2.4)."""
+    c = _wide(M=28, Mv=30, vmax=7.5)
+    o = oracle_mod.Oracle(c)
+    assert o.nv == 28 * 30
+    u = np.linspace(-7.0, 7.0, 28)
+    v = np.linspace(-7.5, 7.5, 30)
+    H0 = np.exp(-u[None, :] ** 2 - v[:, None] ** 2) / np.pi
+    W0, h0, _ = o.state()
+    np.testing.assert_allclose(h0.reshape(c.nc, c.NT, 30, 28), np.broadcast_to(H0, (c.nc, c.NT, 30, 28)),
+                               rtol=1e-13, atol=1e-300)
+    o.step(20)
+    assert np.all(o.residual() < 1e-15)
+    np.testing.assert_allclose(o.state()[1], h0, atol=1e-14)
+
+
 def test_harmonics_of_a_known_state(oracle_mod):
     """Eq. (40): qhat_k = (1/NT) sum_n q_n exp(-i k w t_n).  A state whose
     levels carry rho_n = 1 + A cos(w t_n + phi) has rhohat_1 = (A/2) e^{i phi}."""
