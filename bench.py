@@ -39,17 +39,17 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "c4560ae1d41d6a9c",
+    "sources_sha256_16": "536ac2668f88be2f",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 263704883,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 616566170,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73660928,
-        "shear64_v32_nh1_kn1_st1/mixed/moments": 152952627,
-        "shear64_v32_nh1_kn1_st1/mixed/update_int": 249618534,
-        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38385562,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1084925030,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2223754752,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 272785715,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 264043520,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 615853466,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73707827,
+        "shear64_v32_nh1_kn1_st1/mixed/moments": 152961229,
+        "shear64_v32_nh1_kn1_st1/mixed/update_int": 249509581,
+        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38388019,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1080694784,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2235697050,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 274935091,
     },
 }
 

@@ -22,8 +22,9 @@
  *     the null stream); calls that return host data synchronise that stream.
  * Host array layouts (row-major, last index fastest):
  *   W[c][n][4]  (rho, rho U, rho V, rho E), c = j*nx + i (x fastest)
- *   h, b[c][n][a]  a = iv*M + iu, 1-D nodes u_k of the velocity rule
- *                  (increasing k; hb_vgrid_nodes lists them)
+ *   h, b[c][n][a]  a = iv*M + iu with iu < M along u and iv < M_v along v,
+ *                  the 1-D nodes of each axis increasing (hb_vgrid_nodes
+ *                  lists them)
  */
 #ifndef HB_UGKS_H
 #define HB_UGKS_H
@@ -83,16 +84,22 @@ enum {
                                    the largest node takes its place in Eq. (32) */
 };
 
-/* Square tensor velocity grid: m nodes per axis (m even, 4 <= m <= 128). */
+/* Tensor velocity grid (Sec. 3.1.1): m nodes along u and m_v along v (each
+ * even, 4..128; m_v = 0 takes m), the trapezoid rule on [-umax, umax] along u
+ * and [-vmax, vmax] along v (vmax <= 0 takes umax), or the Gauss-Hermite rule
+ * of m, m_v nodes (umax, vmax unused).  m_v < 0 is HB_EINVAL. */
 typedef struct {
     int m;
     double umax;
     int rule;                 /* HB_RULE_*; zero-initialised = trapezoid */
+    int m_v;                  /* 0 = m (square grid) */
+    double vmax;              /* <= 0: umax */
 } hb_vgrid;
 
-/* The 1-D nodes u[m] (increasing) and weights w[m] of a velocity rule; host
- * only, no device needed.  Errors: HB_EINVAL (NULL, m odd or out of range,
- * unknown rule, umax <= 0 for the trapezoid). */
+/* The 1-D nodes u[m] (increasing) and weights w[m] of the rule along u (m,
+ * umax, rule); the v axis is the same rule with m_v, vmax in place of m, umax.
+ * Host only, no device needed.  Errors: HB_EINVAL (NULL, m odd or out of
+ * range, unknown rule, umax <= 0 for the trapezoid). */
 int hb_vgrid_nodes(const hb_vgrid *vg, double *u, double *w);
 
 typedef struct {
@@ -208,7 +215,8 @@ int hb_ugks_wall_harmonic(hb_handle h, int wall, int var, int k, double out[2]);
 int hb_ugks_state_out(hb_handle h, double *W, double *hh, double *bb, size_t capacity);
 int hb_ugks_state_in(hb_handle h, const double *W, const double *hh, const double *bb);
 
-/* Sizes of the current case: out[0..5] = nx, ny, nc, M, nv (= M*M), NT. */
+/* Sizes of the current case: out[0..5] = nx, ny, nc, M (nodes along u), nv
+ * (= M * M_v), NT. */
 int hb_ugks_sizes(hb_handle h, int out[6]);
 
 /* Device bytes held by the handle. */

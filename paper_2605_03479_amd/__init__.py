@@ -38,7 +38,8 @@ class hb_wall(ctypes.Structure):
 
 
 class hb_vgrid(ctypes.Structure):
-    _fields_ = [("m", ctypes.c_int), ("umax", ctypes.c_double), ("rule", ctypes.c_int)]
+    _fields_ = [("m", ctypes.c_int), ("umax", ctypes.c_double), ("rule", ctypes.c_int), ("m_v", ctypes.c_int),
+                ("vmax", ctypes.c_double)]
 
 
 class hb_numerics(ctypes.Structure):
@@ -181,7 +182,7 @@ def _case_args(case):
     yf = None if case.y_faces is None else np.ascontiguousarray(case.y_faces, np.float64)
     g = hb_geometry(case.L, case.H, case.nx, case.ny, _dp(xf), _dp(yf))
     walls = (hb_wall * 4)(*[hb_wall(*map(float, w)) for w in case.walls])
-    vg = hb_vgrid(case.M, case.umax, case.vrule)
+    vg = hb_vgrid(case.M, case.umax, case.vrule, getattr(case, "Mv", 0), getattr(case, "vmax", 0.0))
     nm = hb_numerics(case.cfl, case.face_dt, case.Pr, case.omega_vss, case.alpha_vss, case.K, case.dt_mode,
                      case.dt_fixed, case.macro_mode, getattr(case, "level_mass", 1))
     return g, walls, vg, nm, (xf, yf)

@@ -88,7 +88,7 @@ struct Shape {
 };
 
 struct UpdGroup {
-    int prec = HB_FP64, NT = 1, M = 0;
+    int prec = HB_FP64, NT = 1, Mt = 0;  // Mt: table stride, max(M, M_v)
     int max_nvp = 0;
     size_t lds = 0;
     DevList in, bn;
@@ -248,7 +248,7 @@ static int grid_of(const hb_batch *B, const DevList &L, int per_cu)
     return per_cu <= 0 ? (int)L.items.size() : per_cu * B->num_cu;
 }
 
-// Work lists of the active cases: cases sorted by (precision, N_T, M) and
+// Work lists of the active cases: cases sorted by (precision, N_T, max(M, M_v)) and
 // packed into cache groups; within a group, in case order then the case's own.
 static int build_lists(hb_batch *B)
 {
@@ -259,7 +259,7 @@ static int build_lists(hb_batch *B)
     std::vector<int> order = B->ids;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const hb_ugks *x = B->cases[a], *y = B->cases[b];
-        return std::make_tuple(x->precision, x->P.NT, x->P.M) < std::make_tuple(y->precision, y->P.NT, y->P.M);
+        return std::make_tuple(x->precision, x->P.NT, x->P.Mt) < std::make_tuple(y->precision, y->P.NT, y->P.Mt);
     });
     for (int s : order) {
         const hb_ugks *H = B->cases[s];
@@ -292,11 +292,11 @@ static int build_lists(hb_batch *B)
         cg.resid.items.push_back({s, 0});
         cg.resid.cost.push_back((double)H->cells_blocks);
         if (cg.groups.empty() || cg.groups.back().prec != H->precision || cg.groups.back().NT != P.NT ||
-            cg.groups.back().M != P.M) {
+            cg.groups.back().Mt != P.Mt) {
             cg.groups.emplace_back();
             cg.groups.back().prec = H->precision;
             cg.groups.back().NT = P.NT;
-            cg.groups.back().M = P.M;
+            cg.groups.back().Mt = P.Mt;
         }
         UpdGroup &g = cg.groups.back();
         g.max_nvp = std::max(g.max_nvp, P.nvp);

@@ -29,17 +29,19 @@ __device__ inline gptr<T> G(gptr<T> p)
 }
 
 struct Params {
-    int nx, ny, nc, M, Mh, Q, Qp, nvp, NT, NH, K, face_dt, dt_mode;
+    // velocity grid: M nodes along u (Mh = M/2), Mv along v (Mvh = Mv/2),
+    // Mt = max(M, Mv) the stride of the per-axis tables
+    int nx, ny, nc, M, Mh, Mv, Mvh, Mt, Q, Qp, nvp, NT, NH, K, face_dt, dt_mode;
     int macro_mode;  // 0: macro flux of Eq. (24); 1: the velocity sum of the micro flux
     int level_mass;  // 1: level-mass projection after each step (see resid_block)
     int ls;  // level stride of h, b in words (nvp plus padding)
-    double omega, mu_ref, omega_vss, Pr, cfl, gamma, umax, dt_fixed;
+    double omega, mu_ref, omega_vss, Pr, cfl, gamma, umax, vmax, dt_fixed;
     double E[HB_NTMAX * HB_NTMAX];
     double wall_ut[4][HB_NTMAX], wall_T[4][HB_NTMAX];
     // geometry
     const double *xf, *yf, *xc, *yc, *rdx, *rdy, *rcx, *rcy;
     // velocity grid: 1-D nodes/weights and per-alpha (internal order) values
-    const double *u1, *w1, *vu, *vv, *vw;
+    const double *u1, *w1, *v1, *w1v, *vu, *vv, *vw;  // 1-D rules along u (M) and v (Mv)
     const int *viu, *viv;
     const double *vref;  // rest Maxwellian per velocity (mixed storage reference)
     const double *rmom;  // per quadrant, sum of w u^a v^b H_ref over its velocities, a + b <= 3 (10 each)
@@ -48,8 +50,8 @@ struct Params {
     // projection factors s_n and (s_n - 1)/pi in FP32, E(u_k) = exp(-u_k^2)
     // in FP64 and FP32, and E of Eq. (17) in FP32
     float *rx32, *ry32, *cr32, *lscale32;
-    const double *ex64;
-    const float *er32;
+    const double *ex64, *ex64v;  // exp(-x^2) at the u nodes, at the v nodes
+    const float *er32, *er32v;
     const float *vel32;  // vu, vv, vw rounded to FP32 (multipliers of the deviations in the moment sums)
     float Ef[HB_NTMAX * HB_NTMAX];
 };

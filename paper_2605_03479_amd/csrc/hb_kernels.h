@@ -338,15 +338,25 @@ __device__ inline cdouble *wave_uniform(Ptr p)
     return (cdouble *)((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-// 1-D sums G[k] = sum_i w_i x_i^k exp(-lam (x_i - U)^2), k = 0..6, over nodes
-// with sign selection sel (0 all, 1 x>0, 2 x<0).
-__device__ inline void gsums(const Params &P, double lam, double U, int sel, double G[7])
+// One axis of the tensor velocity grid: nodes, weights, count
+struct Axis {
+    const double *x, *w;
+    int m;
+};
+__device__ inline Axis axis_u(const Params &P) { return {P.u1, P.w1, P.M}; }
+__device__ inline Axis axis_v(const Params &P) { return {P.v1, P.w1v, P.Mv}; }
+// one 1-D rule serves both axes
+__device__ inline bool square_grid(const Params &P) { return P.Mv == P.M && P.v1 == P.u1; }
+
+// 1-D sums G[k] = sum_i w_i x_i^k exp(-lam (x_i - U)^2), k = 0..6, over m
+// nodes with sign selection sel (0 all, 1 x>0, 2 x<0).
+template <typename Ptr>
+__device__ inline void gsums_at(Ptr u1, Ptr w1, int m, double lam, double U, int sel, double G[7])
 {
 #pragma unroll
     for (int k = 0; k < 7; k++) G[k] = 0.0;
-    cdouble *u1 = wave_uniform(P.u1), *w1 = wave_uniform(P.w1);
 #pragma unroll 4
-    for (int k = 0; k < P.M; k++) {
+    for (int k = 0; k < m; k++) {
         const double x = u1[k];
         if ((sel == 1 && !(x > 0.0)) || (sel == 2 && !(x < 0.0))) continue;
         double t = w1[k] * exp(-lam * (x - U) * (x - U));
@@ -358,12 +368,30 @@ __device__ inline void gsums(const Params &P, double lam, double U, int sel, dou
     }
 }
 
+// gsums_at over the nodes of one axis.  The lanes of a wave can hold faces of
+// both orientations, so the axis varies across the wave unless the grid is
+// square; only then are the nodes read through the scalar unit.
+__device__ inline void gsums(const Params &P, const Axis &A, double lam, double U, int sel, double S[7])
+{
+    if (square_grid(P))
+        gsums_at(wave_uniform(A.x), wave_uniform(A.w), P.M, lam, U, sel, S);
+    else
+        gsums_at(G(A.x), G(A.w), A.m, lam, U, sel, S);
+}
+
 // Two full-range sums of gsums at once (normal and tangential mean of one
 // Maxwellian): the exponentials of both, and of four nodes, are independent,
 // which a one-thread-per-face kernel needs to keep its pipeline busy.  Each
-// sum still accumulates in node order.
-__device__ inline void gsums2(const Params &P, double lam, double Un, double Ut, double Gn[7], double Gt[7])
+// sum still accumulates in node order.  On a square grid both run over the
+// same nodes; otherwise the normal sum runs over An, the tangential over At.
+__device__ inline void gsums2(const Params &P, const Axis &An, const Axis &At, double lam, double Un, double Ut,
+                              double Gn[7], double Gt[7])
 {
+    if (!square_grid(P)) {
+        gsums(P, An, lam, Un, 0, Gn);
+        gsums(P, At, lam, Ut, 0, Gt);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 7; k++) Gn[k] = Gt[k] = 0.0;
     cdouble *u1 = wave_uniform(P.u1), *w1 = wave_uniform(P.w1);
@@ -475,6 +503,8 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
     const int n = t % NT;
     int f = face_of_slot(t / NT, nx, ny);
     bool isx = f < nfx;
+    // the face's normal velocity axis is u on x-faces, v on y-faces
+    const Axis An = isx ? axis_u(P) : axis_v(P), At = isx ? axis_v(P) : axis_u(P);
     int cL, cR, lo_end;  // cells on the low/high side (-1 if wall)
     double xL = 0, xF = 0, xR = 0;
     double *rec;
@@ -568,14 +598,14 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         for (int k = 0; k < 4; k++) rhs[k] = -(r1[k] + r2[k] + r3[k]);
         slope_solve(Un, Ut, lam, K, rhs, A);
         double Gn[7], Gt[7];
-        gsums2(P, lam, Un, Ut, Gn, Gt);
+        gsums2(P, An, At, lam, Un, Ut, Gn, Gt);
         // macro flux: the C2 and C3 parts as Maxwellian moments (Eq. 24), or
         // as the velocity sums of the micro flux's C2 and C3 parts
         double c2a[4], c2b[4], c2c[4], c3[4];
         if (P.macro_mode == 1) {
             double Gp[7], Gm[7];
-            gsums(P, lam, Un, 1, Gp);
-            gsums(P, lam, Un, 2, Gm);
+            gsums(P, An, lam, Un, 1, Gp);
+            gsums(P, An, lam, Un, 2, Gm);
             MomTab d0, dp, dm;
             disc_momtab(Gn, Gt, lam, K, d0);
             disc_momtab(Gp, Gt, lam, K, dp);
@@ -652,8 +682,8 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         else wl = lo_end ? 0 : 2;
         const double Uw = P.wall_ut[wl][n], lw = 1.0 / P.wall_T[wl][n];
         double Gwn[7], Gwt[7];
-        gsums(P, lw, 0.0, refl_side ? 1 : 2, Gwn);
-        gsums(P, lw, Uw, 0, Gwt);
+        gsums(P, An, lw, 0.0, refl_side ? 1 : 2, Gwn);
+        gsums(P, At, lw, Uw, 0, Gwt);
         const double pw = lw / HB_PI, xw = K / (2.0 * lw);
         // reflected half of the unit-density wall Maxwellian: R_ab = sum w n^a t^b H_w
         auto R = [&](int a, int bq) { return pw * Gwn[a] * Gwt[bq]; };
@@ -676,8 +706,8 @@ __device__ inline void faces_thread(const Params &P, const double *__restrict__ 
         Ph.c[0] += 1.0;
         Pb.c[0] += 1.0;
         double Gn[7], Gt[7];
-        gsums(P, lam, Un, inc_side ? 1 : 2, Gn);
-        gsums(P, lam, Ut, 0, Gt);
+        gsums(P, An, lam, Un, inc_side ? 1 : 2, Gn);
+        gsums(P, At, lam, Ut, 0, Gt);
         const double pref = rho * lam / HB_PI;
         double S1[4];
         equil_flux_sums(K, pref, lam, Ph, Pb, Gn, Gt, S1);
@@ -742,7 +772,7 @@ __device__ inline double local_dt(const Params &P, const double *Wc, int i, int 
         double p[4];
         prim4(P.K, Wc + n * 4, p);
         const double cs = sqrt(P.gamma / (2.0 * p[3]));
-        const double ut = fmax(P.umax, fabs(p[1])) + cs, vt = fmax(P.umax, fabs(p[2])) + cs;
+        const double ut = fmax(P.umax, fabs(p[1])) + cs, vt = fmax(P.vmax, fabs(p[2])) + cs;
         nu = fmax(nu, ut * P.rdx[i] + vt * P.rdy[j]);
     }
     return P.cfl / (nu + P.omega * P.NH);
@@ -994,18 +1024,33 @@ __device__ inline void face_flux(Ptr s, double e, double un, double ut, double h
 template <int NT>
 __device__ inline void build_tables(const Params &P, const gptr<const double> fr[4], gptr<const double> cr, double *tab)
 {
-    const int M = P.M, ftab = 12 * NT * M;
+    const int M = P.Mt, ftab = 12 * NT * M;
     for (int t = threadIdx.x; t < 16 * NT * M; t += blockDim.x) {
         const int k = t % M;
-        const double x = G(P.u1)[k];
+        bool onv;  // the row runs over the v nodes
+        int which, n, fs = 0;
+        if (t < ftab) {
+            which = (t / M) % 3;
+            const int fn = t / (3 * M);
+            n = fn % NT;
+            fs = fn / NT;
+            onv = (fs >= 2) == (which == 0);  // x-faces: normal u, tangential v; y-faces the reverse
+        } else {
+            which = ((t - ftab) / M) % 4;
+            n = (t - ftab) / (4 * M);
+            onv = which & 1;
+        }
+        if (k >= (onv ? P.Mv : P.M)) {
+            tab[t] = 0.0;  // stride padding of the shorter axis, never read
+            continue;
+        }
+        const double x = onv ? G(P.v1)[k] : G(P.u1)[k];
         double lam, U;
         if (t < ftab) {
-            const int which = (t / M) % 3, fn = t / (3 * M), n = fn % NT, fs = fn / NT;
             const gptr<const double> sd = fr[fs] + n * REC + REC_SIDE + REC_SIDEW * (which == 0 ? (x > 0.0 ? 1 : 0) : which - 1);
             lam = sd[0];
             U = which == 0 ? sd[1] : sd[2];
         } else {
-            const int tt = t - ftab, which = (tt / M) % 4, n = tt / (4 * M);
             const gptr<const double> cc = cr + n * CREC + (which >= 2 ? CREC_T : 0);
             lam = cc[0];
             U = (which & 1) ? cc[2] : cc[1];
@@ -1030,7 +1075,7 @@ __device__ inline void collide_store(const Params &P, gptr<const double> cr, con
                                      double v, int iu, int iv, const double *hk, const double *bk, const double *dh,
                                      const double *db, TS *hn, TS *bn, long e0, double rh, double rb)
 {
-    const int M = P.M;
+    const int M = P.Mt;  // table row stride
     const double kh = P.K - 5.0, kb = P.K - 3.0, dgw = dG * P.omega;
 #pragma unroll
     for (int n = 0; n < NT; n++) {
@@ -1081,7 +1126,7 @@ __device__ inline void update_int_cell_d(const Params &P, const TS *__restrict__
     extern __shared__ double tab[];
     const int nxi = P.nx - 4;
     const int i = 2 + ci % nxi, j = 2 + ci / nxi;
-    const int M = P.M, nx = P.nx;
+    const int M = P.Mt, nx = P.nx;
     const int c = j * nx + i;
     scale_w<NT>(P, Wn, c);
     const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
@@ -1185,7 +1230,7 @@ __device__ inline void update_bnd_cell_d(const Params &P, const TS *__restrict__
                                        TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int c)
 {
     extern __shared__ double tab[];
-    const int M = P.M, nx = P.nx, ny = P.ny;
+    const int M = P.Mt, nx = P.nx, ny = P.ny;
     const int i = c % nx, j = c / nx;
     scale_w<NT>(P, Wn, c);
     const gptr<const double> fr[4] = {G(recx) + (long)(j * (nx + 1) + i) * NT * REC, G(recx) + (long)(j * (nx + 1) + i + 1) * NT * REC,
@@ -1414,10 +1459,11 @@ __global__ void k_restmom(Params P, double *rmom)
 // E(u_k) = exp(-u_k^2) of the 1-D nodes, in FP64 (the reference the mixed
 // form's deviation tables subtract; the same expression as the tables' own
 // exponential at lam = 1, U = 0) and rounded to FP32 (multipliers)
+// (the u nodes, then the v nodes)
 __global__ void k_etab(Params P, double *ex64, float *er32)
 {
-    for (int k = threadIdx.x; k < P.M; k += blockDim.x) {
-        const double x = P.u1[k], e = exp(-x * x);
+    for (int k = threadIdx.x; k < P.M + P.Mv; k += blockDim.x) {
+        const double x = k < P.M ? P.u1[k] : P.v1[k - P.M], e = exp(-x * x);
         ex64[k] = e;
         er32[k] = static_cast<float>(e);
     }

@@ -96,24 +96,39 @@ template <int NT>
 __device__ inline void build_tables_m(const Params &P, const gptr<const double> fr[4], gptr<const double> cr,
                                       float *tab)
 {
-    const int M = P.M, ftab = 12 * NT * M;
+    const int M = P.Mt, ftab = 12 * NT * M;
     for (int t = threadIdx.x; t < 16 * NT * M; t += blockDim.x) {
         const int k = t % M;
-        const double x = G(P.u1)[k];
+        bool onv;  // the row runs over the v nodes
+        int which, n, fs = 0;
+        if (t < ftab) {
+            which = (t / M) % 3;
+            const int fn = t / (3 * M);
+            n = fn % NT;
+            fs = fn / NT;
+            onv = (fs >= 2) == (which == 0);  // x-faces: normal u, tangential v; y-faces the reverse
+        } else {
+            which = ((t - ftab) / M) % 4;
+            n = (t - ftab) / (4 * M);
+            onv = which & 1;
+        }
+        if (k >= (onv ? P.Mv : P.M)) {
+            tab[t] = 0.0f;  // stride padding of the shorter axis, never read
+            continue;
+        }
+        const double x = onv ? G(P.v1)[k] : G(P.u1)[k];
         double lam, U;
         if (t < ftab) {
-            const int which = (t / M) % 3, fn = t / (3 * M), n = fn % NT, fs = fn / NT;
             const gptr<const double> sd =
                 fr[fs] + n * REC + REC_SIDE + REC_SIDEW * (which == 0 ? (x > 0.0 ? 1 : 0) : which - 1);
             lam = sd[0];
             U = which == 0 ? sd[1] : sd[2];
         } else {
-            const int tt = t - ftab, which = (tt / M) % 4, n = tt / (4 * M);
             const gptr<const double> cc = cr + n * CREC + (which >= 2 ? CREC_T : 0);
             lam = cc[0];
             U = (which & 1) ? cc[2] : cc[1];
         }
-        tab[t] = static_cast<float>(exp(-lam * (x - U) * (x - U)) - G(P.ex64)[k]);
+        tab[t] = static_cast<float>(exp(-lam * (x - U) * (x - U)) - (onv ? G(P.ex64v)[k] : G(P.ex64)[k]));
     }
 }
 
@@ -126,7 +141,7 @@ __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float 
                                        const float *hk, const float *bk, const float *dh, const float *db,
                                        float *__restrict__ hn, float *__restrict__ bn, long e0)
 {
-    const int M = P.M;
+    const int M = P.Mt;  // table row stride
     const float kh = P.K - 5.0f;
     cfloat *ls = wave_uniform_f(P.lscale32);
 #pragma unroll
@@ -393,7 +408,7 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
     extern __shared__ float tabf[];
     const int nxi = P.nx - 4;
     const int i = 2 + ci % nxi, j = 2 + ci / nxi;
-    const int M = P.M, nx = P.nx;
+    const int M = P.Mt, nx = P.nx;
     const int c = j * nx + i;
     scale_w<NT>(P, Wn, c);
     const long fw = (long)(j * (nx + 1) + i) * NT, fe = fw + NT, fs = (long)(j * nx + i) * NT,
@@ -430,7 +445,7 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
         if (r >= P.Q) continue;
         const float u = static_cast<float>(G(P.vu)[ap]), v = static_cast<float>(G(P.vv)[ap]);
         const int iu = G(P.viu)[ap], iv = G(P.viv)[ap];
-        const float eru = G(P.er32)[iu], erv = G(P.er32)[iv], href = eru * erv;
+        const float eru = G(P.er32)[iu], erv = G(P.er32v)[iv], href = eru * erv;
         const Mono m = mono_of(u, v);
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0f ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0f ? 1 : 0);
@@ -540,7 +555,7 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
                                          int c)
 {
     extern __shared__ float tabf[];
-    const int M = P.M, nx = P.nx, ny = P.ny;
+    const int M = P.Mt, nx = P.nx, ny = P.ny;
     const int i = c % nx, j = c / nx;
     scale_w<NT>(P, Wn, c);
     const long fw = (long)(j * (nx + 1) + i) * NT, fe = fw + NT, fs = (long)(j * nx + i) * NT,
@@ -576,7 +591,7 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
         if (r >= P.Q) continue;
         const float u = static_cast<float>(G(P.vu)[ap]), v = static_cast<float>(G(P.vv)[ap]);
         const int iu = G(P.viu)[ap], iv = G(P.viv)[ap];
-        const float eru = G(P.er32)[iu], erv = G(P.er32)[iv], href = eru * erv;
+        const float eru = G(P.er32)[iu], erv = G(P.er32v)[iv], href = eru * erv;
         const Mono m = mono_of(u, v);
         const int su = __builtin_amdgcn_readfirstlane(u > 0.0f ? 1 : 0);
         const int sv = __builtin_amdgcn_readfirstlane(v > 0.0f ? 1 : 0);

@@ -77,20 +77,19 @@ static void hermite_fn(int n, double x, double &pm1, double &pn)
 // sum_k w_k f(u_k) approximates the plain integral of f.  Positive roots are
 // bracketed by a scan finer than a tenth of the smallest root spacing
 // (about pi / sqrt(2 m)), then bisected to the last bit.
-static int velocity_rule(const hb_vgrid *vg, double *u, double *w)
+static int velocity_rule(int m, double umax, int rule, double *u, double *w)
 {
-    const int m = vg->m;
     if (m < 4 || m > 128 || (m & 1)) return HB_EINVAL;
-    if (vg->rule == HB_RULE_TRAPEZOID) {
-        if (!(vg->umax > 0.0)) return HB_EINVAL;
-        const double du = 2.0 * vg->umax / (m - 1);
+    if (rule == HB_RULE_TRAPEZOID) {
+        if (!(umax > 0.0)) return HB_EINVAL;
+        const double du = 2.0 * umax / (m - 1);
         for (int k = 0; k < m; k++) {
-            u[k] = -vg->umax + k * du;
+            u[k] = -umax + k * du;
             w[k] = (k == 0 || k == m - 1) ? 0.5 * du : du;
         }
         return HB_OK;
     }
-    if (vg->rule != HB_RULE_GAUSS_HERMITE) return HB_EINVAL;
+    if (rule != HB_RULE_GAUSS_HERMITE) return HB_EINVAL;
     const int half = m / 2;
     const double xend = std::sqrt(2.0 * m + 1.0) + 1.0, step = 0.1 * M_PI / std::sqrt(2.0 * m + 1.0);
     int found = 0;
@@ -258,7 +257,7 @@ const char *hb_ugks_strerror(int s)
 int hb_vgrid_nodes(const hb_vgrid *vg, double *u, double *w)
 {
     if (!vg || !u || !w) return HB_EINVAL;
-    return velocity_rule(vg, u, w);
+    return velocity_rule(vg->m, vg->umax, vg->rule, u, w);
 }
 
 int hb_ugks_create(const hb_create_opts *opts, hb_handle *out)
@@ -310,8 +309,10 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     hb_numerics nm;
     hb_ugks_default_numerics(&nm);
     if (num) nm = *num;
-    const int nx = g->nx, ny = g->ny, M = vg->m;
-    if (nx < 3 || ny < 3 || M < 4 || M > 128 || (M & 1) || NH < 0 || 2 * NH + 1 > HB_NTMAX || !(Kn > 0.0) ||
+    const int nx = g->nx, ny = g->ny, M = vg->m, Mv = vg->m_v ? vg->m_v : vg->m;
+    const double vmax = vg->vmax > 0.0 ? vg->vmax : vg->umax;
+    if (nx < 3 || ny < 3 || M < 4 || M > 128 || (M & 1) || Mv < 4 || Mv > 128 || (Mv & 1) || NH < 0 ||
+        2 * NH + 1 > HB_NTMAX || !(Kn > 0.0) ||
         !(St >= 0.0) || (vg->rule != HB_RULE_TRAPEZOID && vg->rule != HB_RULE_GAUSS_HERMITE) ||
         (vg->rule == HB_RULE_TRAPEZOID && !(vg->umax > 0.0)) || !(nm.cfl > 0.0) || nm.K_int < 0 || !(nm.Pr > 0.0) ||
         (nm.dt_mode == 1 && !(nm.dt_fixed > 0.0)) || !(g->L > 0.0) || !(g->H > 0.0) ||
@@ -337,7 +338,10 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.nc = nx * ny;
     P.M = M;
     P.Mh = M / 2;
-    P.Q = P.Mh * P.Mh;
+    P.Mv = Mv;
+    P.Mvh = Mv / 2;
+    P.Mt = std::max(M, Mv);
+    P.Q = P.Mh * P.Mvh;
     P.Qp = (P.Q + 63) / 64 * 64;
     P.nvp = 4 * P.Qp;
     P.ls = P.nvp;
@@ -359,7 +363,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.Pr = nm.Pr;
     P.cfl = nm.cfl;
     P.gamma = (P.K + 4.0) / (P.K + 2.0);
-    P.umax = vg->umax;  // the Gauss-Hermite rule replaces it by its largest node below
+    P.umax = vg->umax;  // the Gauss-Hermite rule replaces both by their largest nodes below
+    P.vmax = vmax;
     const int NT = P.NT;
     for (int n = 0; n < NT; n++)
         for (int m = 0; m < NT; m++) {
@@ -380,7 +385,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     std::vector<double> geo;
     geo.insert(geo.end(), xf.begin(), xf.end());
     geo.insert(geo.end(), yf.begin(), yf.end());
-    std::vector<double> xc(nx), yc(ny), rdx(nx), rdy(ny), rcx(nx, 0.0), rcy(ny, 0.0), u1(M), w1(M);
+    std::vector<double> xc(nx), yc(ny), rdx(nx), rdy(ny), rcx(nx, 0.0), rcy(ny, 0.0), u1(M), w1(M), v1(Mv), w1v(Mv);
     for (int i = 0; i < nx; i++) {
         xc[i] = 0.5 * (xf[i] + xf[i + 1]);
         rdx[i] = 1.0 / (xf[i + 1] - xf[i]);
@@ -391,8 +396,15 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     }
     for (int i = 1; i < nx; i++) rcx[i] = 1.0 / (xc[i] - xc[i - 1]);
     for (int j = 1; j < ny; j++) rcy[j] = 1.0 / (yc[j] - yc[j - 1]);
-    if (velocity_rule(vg, u1.data(), w1.data()) != HB_OK) return HB_EINVAL;
-    if (vg->rule == HB_RULE_GAUSS_HERMITE) P.umax = u1[M - 1];
+    if (velocity_rule(M, vg->umax, vg->rule, u1.data(), w1.data()) != HB_OK ||
+        velocity_rule(Mv, vmax, vg->rule, v1.data(), w1v.data()) != HB_OK)
+        return HB_EINVAL;
+    if (vg->rule == HB_RULE_GAUSS_HERMITE) {
+        P.umax = u1[M - 1];
+        P.vmax = v1[Mv - 1];
+    }
+    // a square grid keeps one 1-D rule for both axes
+    const bool square = Mv == M && v1 == u1;
     const size_t ox_xc = geo.size();
     geo.insert(geo.end(), xc.begin(), xc.end());
     const size_t ox_yc = geo.size();
@@ -409,21 +421,25 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     geo.insert(geo.end(), u1.begin(), u1.end());
     const size_t ox_w1 = geo.size();
     geo.insert(geo.end(), w1.begin(), w1.end());
+    const size_t ox_v1 = square ? ox_u1 : geo.size();
+    if (!square) geo.insert(geo.end(), v1.begin(), v1.end());
+    const size_t ox_w1v = square ? ox_w1 : geo.size();
+    if (!square) geo.insert(geo.end(), w1v.begin(), w1v.end());
 
     // internal velocity order: quadrant q = (u>0) + 2 (v>0), then (iv, iu) inside it, 64-padded
     const int Mh = P.Mh, Qp = P.Qp, nvp = P.nvp;
     std::vector<double> vel(3 * (size_t)nvp, 0.0);
     std::vector<int> veli(2 * (size_t)nvp, 0);
-    H->perm.assign((size_t)M * M, -1);
+    H->perm.assign((size_t)M * Mv, -1);
     for (int q = 0; q < 4; q++)
         for (int r = 0; r < Qp; r++) {
             const int rr = r < P.Q ? r : 0;  // padding repeats the first velocity with zero weight
             const int il = rr % Mh, jl = rr / Mh;
-            const int iu = (q & 1) ? Mh + il : il, iv = (q & 2) ? Mh + jl : jl;
+            const int iu = (q & 1) ? Mh + il : il, iv = (q & 2) ? P.Mvh + jl : jl;
             const int ap = q * Qp + r;
             vel[ap] = u1[iu];
-            vel[nvp + ap] = u1[iv];
-            vel[2 * (size_t)nvp + ap] = r < P.Q ? w1[iu] * w1[iv] : 0.0;
+            vel[nvp + ap] = v1[iv];
+            vel[2 * (size_t)nvp + ap] = r < P.Q ? w1[iu] * w1v[iv] : 0.0;
             veli[ap] = iu;
             veli[nvp + ap] = iv;
             if (r < P.Q) H->perm[(size_t)iv * M + iu] = ap;
@@ -432,7 +448,7 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     const size_t nel = (size_t)P.nc * NT * P.ls;
     const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     H->cells_blocks = (P.nc * NT + 127) / 128;
-    H->upd_lds = (H->precision == HB_MIXED ? sizeof(float) : sizeof(double)) * 16 * (size_t)NT * M;
+    H->upd_lds = (H->precision == HB_MIXED ? sizeof(float) : sizeof(double)) * 16 * (size_t)NT * P.Mt;
     if (H->upd_lds > 160 * 1024) return HB_EINVAL;
     int rc = HB_OK;
 #define ALLOC(ptr, count, T)                                            \
@@ -468,8 +484,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
         ALLOC(H->rx32, nfx * NT * hb::REC32, float);
         ALLOC(H->ry32, nfy * NT * hb::REC32, float);
         ALLOC(H->cr32, (size_t)P.nc * NT * hb::CREC32, float);
-        ALLOC(H->ex64, M, double);
-        ALLOC(H->er32, M, float);
+        ALLOC(H->ex64, M + Mv, double);
+        ALLOC(H->er32, M + Mv, float);
         ALLOC(H->vel32, vel.size(), float);
     }
     ALLOC(H->ring, (size_t)HB_RING * 4, double);
@@ -534,6 +550,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
     P.rcy = H->geo + ox_rcy;
     P.u1 = H->geo + ox_u1;
     P.w1 = H->geo + ox_w1;
+    P.v1 = H->geo + ox_v1;
+    P.w1v = H->geo + ox_w1v;
     P.vu = H->vel;
     P.vv = H->vel + nvp;
     P.vw = H->vel + 2 * (size_t)nvp;
@@ -549,6 +567,8 @@ int hb_ugks_set_case(hb_handle H, const hb_geometry *g, double Kn, double St, in
         P.lscale32 = (float *)(H->lscale + HB_NTMAX);
         P.ex64 = H->ex64;
         P.er32 = H->er32;
+        P.ex64v = H->ex64 + M;
+        P.er32v = H->er32 + M;
         P.vel32 = H->vel32;
         for (int k = 0; k < NT * NT; k++) P.Ef[k] = static_cast<float>(P.E[k]);
     }
@@ -765,7 +785,7 @@ int hb_ugks_sizes(hb_handle H, int out[6])
     out[1] = H->P.ny;
     out[2] = H->P.nc;
     out[3] = H->P.M;
-    out[4] = H->P.M * H->P.M;
+    out[4] = H->P.M * H->P.Mv;
     out[5] = H->P.NT;
     return HB_OK;
 }
@@ -777,7 +797,7 @@ int hb_ugks_state_out(hb_handle H, double *W, double *hh, double *bb, size_t cap
     if (!H) return HB_EINVAL;
     if (!H->has_case) return HB_ESTATE;
     const hb::Params &P = H->P;
-    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.M;
+    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.Mv;
     if ((hh || bb) && capacity < ncn * nv) return HB_ECAPACITY;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
@@ -807,7 +827,7 @@ int hb_ugks_state_in(hb_handle H, const double *W, const double *hh, const doubl
     if (!H) return HB_EINVAL;
     if (!H->has_case) return HB_ESTATE;
     const hb::Params &P = H->P;
-    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.M;
+    const size_t ncn = (size_t)P.nc * P.NT, nv = (size_t)P.M * P.Mv;
     if (hipSetDevice(H->device) != hipSuccess) return HB_EDEVICE;
     HIPOK(H->stream ? hipStreamSynchronize(H->stream) : hipDeviceSynchronize());
     if (W) HIPOK(hipMemcpy(H->W[H->cur], W, ncn * 4 * sizeof(double), hipMemcpyHostToDevice));

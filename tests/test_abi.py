@@ -32,6 +32,47 @@ def test_exports_every_declared_symbol(lib):
     assert set(names) == set(hb.EXPORTS)
 
 
+def _header_structs():
+    """{name: [field, ...]} of every typedef struct in the header."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "hb_ugks.h")).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", src, flags=re.S):
+        fields = []
+        for decl in filter(None, (d.strip() for d in body.split(";"))):
+            decl = re.sub(r"\[[^\]]*\]", "", decl)
+            m = re.match(r"((?:const\s+)?(?:unsigned\s+)?\w+(?:\s*\*)*)\s+(.*)", decl, flags=re.S)
+            fields += [re.sub(r"[\s*]", "", x) for x in m.group(2).split(",")]
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs: same fields in the same
+    order, and the same size and offsets as the C compiler lays them out."""
+    structs = _header_structs()
+    assert {"hb_vgrid", "hb_geometry", "hb_wall", "hb_numerics", "hb_request", "hb_result"} <= set(structs)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hb_ugks.h"', "int main(void) {"]
+    for name, fields in structs.items():
+        cls = getattr(hb, name)
+        assert [f[0] for f in cls._fields_] == fields, name
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, fields in structs.items():
+        cls = getattr(hb, name)
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in fields:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
 def test_strerror_and_defaults(lib):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.hb_ugks_strerror(code)

@@ -35,6 +35,9 @@ CASES = [
     # Gauss-Hermite velocities on a wall-refined mesh
     (Case(10, 9, 14, 0.0, 0.1, 3.0, 1, hbcases.lid_walls(0.01), x_faces=hbcases.stretched_faces(10, 1.0, 0.02),
           y_faces=hbcases.stretched_faces(9, 1.0, 0.02), vrule=1), 0),
+    # rectangular velocity grids: wider along v (mixed), wider along u (FP64)
+    (Case(8, 10, 12, 4.0, 0.5, 2.0, 1, hbcases.lid_walls(0.01), Mv=20, vmax=5.0), 1),
+    (Case(9, 8, 22, 5.0, 0.2, 1.0, 2, hbcases.thermal_walls(0.3, 0, "sin"), Mv=10, vmax=4.0), 0),
 ]
 
 

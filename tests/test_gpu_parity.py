@@ -225,6 +225,36 @@ def test_gauss_hermite_grid(gpu, oracle_mod, prec, tol):
     s.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(0, TOL), (1, 1e-6)], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("grid", [dict(M=10, umax=4.0, Mv=16, vmax=5.0), dict(M=18, umax=5.0, Mv=8, vmax=4.0),
+                                  dict(M=12, umax=0.0, Mv=16, vrule=1)], ids=["v-wider", "u-wider", "gh12x16"])
+def test_rectangular_velocity_grid(gpu, oracle_mod, prec, tol, grid):
+    """Velocity grids with a different node count and range along u and v
+    (the trapezoid rule, and the Gauss-Hermite rule of 12 x 16 nodes): the
+    face tables take the normal axis of each face, the collision tables both,
+    the CFL bound each axis's extent.  A lid, a sliding wall and a heated
+    wall on rectangular cells; every element after 1 and 6 steps."""
+    w = [list(r) for r in hbcases.lid_walls(0.03)]
+    w[0][4] = 0.12
+    w[3][1] = 0.02
+    case = Case(7, 6, Kn=0.2, St=2.0, NH=1, walls=tuple(map(tuple, w)), L=1.3,
+                y_faces=(0.0, 0.1, 0.3, 0.55, 0.75, 0.9, 1.0), name="rect", **grid)
+    st = _perturbed(oracle_mod, case, 5150 + case.M)
+    o = oracle_mod.Oracle(case)
+    o.set_state(*st)
+    s = gpu.Solver(case, precision=prec)
+    s.set_state(*st)
+    assert s.sizes[4] == case.M * case.Mv_
+    rest = _rest_like(o.state())
+    done = 0
+    for k in (1, 6):
+        o.step(k - done)
+        s.step(k - done)
+        done = k
+        _compare_states(s.state(), o.state(), rest, tol=tol, what=f"{grid} prec {prec} step {k}")
+    s.close()
+
+
 @pytest.mark.parametrize("nx,ny,M,NH", [(3, 3, 4, 0), (4, 3, 6, 5), (5, 5, 4, 3), (3, 6, 8, 1)])
 def test_degenerate_sizes(gpu, oracle_mod, nx, ny, M, NH):
     """The smallest grids (every cell in the boundary ring, or one interior
