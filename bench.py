@@ -39,17 +39,17 @@ KERNEL_SOURCES = ("paper_2605_03479_amd/csrc/hb_kernels.h", "paper_2605_03479_am
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per dispatch x 1024 x calibration
 # (fetch x2.0, write x1.0 from a 256 MiB copy), averaged over the profiled launches
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "536ac2668f88be2f",
+    "sources_sha256_16": "d6f78dbca9155cd5",
     "bytes": {
-        "shear64_v32_nh1_kn1_st1/fp64/moments": 264043520,
-        "shear64_v32_nh1_kn1_st1/fp64/update_int": 615853466,
-        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73707827,
-        "shear64_v32_nh1_kn1_st1/mixed/moments": 152961229,
-        "shear64_v32_nh1_kn1_st1/mixed/update_int": 249509581,
-        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38388019,
-        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1080694784,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2235697050,
-        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 274935091,
+        "shear64_v32_nh1_kn1_st1/fp64/moments": 263871898,
+        "shear64_v32_nh1_kn1_st1/fp64/update_int": 617515315,
+        "shear64_v32_nh1_kn1_st1/fp64/update_bnd": 73693901,
+        "shear64_v32_nh1_kn1_st1/mixed/moments": 152945766,
+        "shear64_v32_nh1_kn1_st1/mixed/update_int": 247780250,
+        "shear64_v32_nh1_kn1_st1/mixed/update_bnd": 38398259,
+        "thermal64_v48_nh4_kn1_st1/mixed/moments": 1082988544,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_int": 2144916070,
+        "thermal64_v48_nh4_kn1_st1/mixed/update_bnd": 257197773,
     },
 }
 
@@ -383,6 +383,27 @@ def timed_run(hb, case, prec, stream, sync, steps, warmup):
     return (t1 - t0) * 1e3 / steps, kt, res
 
 
+def timed_median(hb, case, prec, stream, sync, steps, warmup, reps=3):
+    """Median of `reps` timings of `steps` pseudo steps on one handle (ms per
+    step), so that one stalled segment of a short sweep point does not stand
+    for the point."""
+    s = hb.Solver(case, device=0, stream=stream, precision=prec)
+    s.step(warmup)
+    s.residual()
+    if sync:
+        sync()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.residual()
+        if sync:
+            sync()
+        t.append((time.perf_counter() - t0) * 1e3 / steps)
+    s.close()
+    return sorted(t)[len(t) // 2]
+
+
 def host_cpu():
     """CPU model and logical CPUs of this host (for the oracle baseline)."""
     model = None
@@ -636,14 +657,14 @@ def main():
             for st in hbcases.SHEAR_ST:
                 c3 = hbcases.shear_cavity(kn, st)
                 for p3, pn in ((hb.HB_FP64, "fp64"), (hb.HB_MIXED, "mixed")):
-                    ms3, _, _ = timed_run(hb, c3, p3, stream, sync, 30, 5)
+                    ms3 = timed_median(hb, c3, p3, stream, sync, 30, 5)
                     knst.append({"workload": c3.name, "precision": pn, "Kn": kn, "St": st, "ms_per_step": ms3,
                                  "updates_per_s": c3.updates / (ms3 * 1e-3)})
         log("shear Kn x St: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst))
         for kn in hbcases.THERMAL_KN:
             for st in hbcases.THERMAL_ST:
                 c3 = hbcases.thermal_cavity(kn, st)
-                ms3, _, _ = timed_run(hb, c3, hb.HB_MIXED, stream, sync, 20, 5)
+                ms3 = timed_median(hb, c3, hb.HB_MIXED, stream, sync, 20, 5)
                 knst.append({"workload": c3.name, "precision": "mixed", "Kn": kn, "St": st, "ms_per_step": ms3,
                              "updates_per_s": c3.updates / (ms3 * 1e-3)})
         log("thermal Kn x St: ms/step " + " ".join(f"{d['ms_per_step']:.3f}" for d in knst[-4:]))

@@ -89,6 +89,7 @@ struct Shape {
 
 struct UpdGroup {
     int prec = HB_FP64, NT = 1, Mt = 0;  // Mt: table stride, max(M, M_v)
+    bool so = false;                     // non-temporal stores of the update (the cases' Params::stream_out)
     int max_nvp = 0;
     size_t lds = 0;
     DevList in, bn;
@@ -98,16 +99,25 @@ struct UpdGroup {
 // tuner memory: (precision, NT, nvp) -> shape of the update phase; (precision, 0, nvp) -> moments
 std::map<std::tuple<int, int, int>, Shape> g_tuned;
 
+template <int NT, typename TS, bool SO>
+int set_batch_lds_so(size_t bytes)
+{
+    if (hipFuncSetAttribute((const void *)hb::kb_update_int<NT, TS, SO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess ||
+        hipFuncSetAttribute((const void *)hb::kb_update_bnd<NT, TS, SO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess)
+        return HB_EDEVICE;
+    return HB_OK;
+}
 template <int NT, typename TS>
 int set_batch_lds_t(size_t bytes)
 {
     if (bytes <= 64 * 1024) return HB_OK;
-    if (hipFuncSetAttribute((const void *)hb::kb_update_int<NT, TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) != hipSuccess ||
-        hipFuncSetAttribute((const void *)hb::kb_update_bnd<NT, TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) != hipSuccess)
-        return HB_EDEVICE;
-    return HB_OK;
+    const int rc = set_batch_lds_so<NT, TS, false>(bytes);
+    if constexpr (sizeof(TS) == 4) {
+        if (rc == HB_OK) return set_batch_lds_so<NT, TS, true>(bytes);
+    }
+    return rc;
 }
 
 template <typename TS>
@@ -123,16 +133,28 @@ int set_batch_lds_p(int NT, size_t bytes)
     }
 }
 
+template <int NT, typename TS, bool SO>
+void launch_group_so(const UpdGroup &g, const CaseDev *cs, const CaseCtl *ctl, hipStream_t st, bool interior,
+                     bool ring)
+{
+    if (interior && g.in.grid)
+        hipLaunchKernelGGL((hb::kb_update_int<NT, TS, SO>), dim3(g.in.grid), dim3(g.in.tpb), g.lds, st, cs, ctl,
+                           g.in.d_items, g.in.d_bstart);
+    if (ring && g.bn.grid)
+        hipLaunchKernelGGL((hb::kb_update_bnd<NT, TS, SO>), dim3(g.bn.grid), dim3(g.bn.tpb), g.lds, st, cs, ctl,
+                           g.bn.d_items, g.bn.d_bstart);
+}
 template <int NT, typename TS>
 void launch_group_t(const UpdGroup &g, const CaseDev *cs, const CaseCtl *ctl, hipStream_t st, bool interior,
                     bool ring)
 {
-    if (interior && g.in.grid)
-        hipLaunchKernelGGL((hb::kb_update_int<NT, TS>), dim3(g.in.grid), dim3(g.in.tpb), g.lds, st, cs, ctl,
-                           g.in.d_items, g.in.d_bstart);
-    if (ring && g.bn.grid)
-        hipLaunchKernelGGL((hb::kb_update_bnd<NT, TS>), dim3(g.bn.grid), dim3(g.bn.tpb), g.lds, st, cs, ctl,
-                           g.bn.d_items, g.bn.d_bstart);
+    if constexpr (sizeof(TS) == 4) {
+        if (g.so) {
+            launch_group_so<NT, TS, true>(g, cs, ctl, st, interior, ring);
+            return;
+        }
+    }
+    launch_group_so<NT, TS, false>(g, cs, ctl, st, interior, ring);
 }
 
 template <typename TS>
@@ -259,7 +281,8 @@ static int build_lists(hb_batch *B)
     std::vector<int> order = B->ids;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const hb_ugks *x = B->cases[a], *y = B->cases[b];
-        return std::make_tuple(x->precision, x->P.NT, x->P.Mt) < std::make_tuple(y->precision, y->P.NT, y->P.Mt);
+        return std::make_tuple(x->precision, x->P.NT, x->P.Mt, x->P.stream_out) <
+               std::make_tuple(y->precision, y->P.NT, y->P.Mt, y->P.stream_out);
     });
     for (int s : order) {
         const hb_ugks *H = B->cases[s];
@@ -292,11 +315,12 @@ static int build_lists(hb_batch *B)
         cg.resid.items.push_back({s, 0});
         cg.resid.cost.push_back((double)H->cells_blocks);
         if (cg.groups.empty() || cg.groups.back().prec != H->precision || cg.groups.back().NT != P.NT ||
-            cg.groups.back().Mt != P.Mt) {
+            cg.groups.back().Mt != P.Mt || cg.groups.back().so != (P.stream_out != 0)) {
             cg.groups.emplace_back();
             cg.groups.back().prec = H->precision;
             cg.groups.back().NT = P.NT;
             cg.groups.back().Mt = P.Mt;
+            cg.groups.back().so = P.stream_out != 0;
         }
         UpdGroup &g = cg.groups.back();
         g.max_nvp = std::max(g.max_nvp, P.nvp);

@@ -111,7 +111,9 @@ __global__ __launch_bounds__(256) void kb_resid(const CaseDev *__restrict__ cs, 
     }
 }
 
-template <int NT, typename TS>
+// SO: every case of the work list stores its update non-temporally (the group
+// is formed per store policy)
+template <int NT, typename TS, bool SO = false>
 __global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_WAVES) void kb_update_int(const CaseDev *__restrict__ cs,
                                                                     const CaseCtl *__restrict__ ctl,
                                                                     const WorkItem *__restrict__ items,
@@ -123,13 +125,13 @@ __global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_
         const WorkItem w = items[it];
         const CaseDev &C = cs[w.cs];
         const int cur = ctl[w.cs].cur;
-        update_int_cell<NT, TS>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
+        update_int_cell<NT, TS, SO ? OUT_NT : 0>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
                                 (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], C.W[1 - cur], w.unit);
         __syncthreads();
     }
 }
 
-template <int NT, typename TS>
+template <int NT, typename TS, bool SO = false>
 __global__ __launch_bounds__(256, 2) void kb_update_bnd(const CaseDev *__restrict__ cs, const CaseCtl *__restrict__ ctl,
                                                         const WorkItem *__restrict__ items,
                                                         const int *__restrict__ bstart)
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256, 2) void kb_update_bnd(const CaseDev *__restric
         const WorkItem w = items[it];
         const CaseDev &C = cs[w.cs];
         const int cur = ctl[w.cs].cur;
-        update_bnd_cell<NT, TS>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
+        update_bnd_cell<NT, TS, SO ? OUT_NT : 0>(C.P, (const TS *)C.h[cur], (const TS *)C.b[cur], C.recx, C.recy, C.crec, C.dt[cur],
                                 (TS *)C.h[1 - cur], (TS *)C.b[1 - cur], C.W[1 - cur], w.unit);
         __syncthreads();
     }

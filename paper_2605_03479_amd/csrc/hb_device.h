@@ -35,6 +35,7 @@ struct Params {
     int macro_mode;  // 0: macro flux of Eq. (24); 1: the velocity sum of the micro flux
     int level_mass;  // 1: level-mass projection after each step (see resid_block)
     int ls;  // level stride of h, b in words (nvp plus padding)
+    int stream_out;  // 1: the update stores h, b past the caches (the state exceeds the last-level cache)
     double omega, mu_ref, omega_vss, Pr, cfl, gamma, umax, vmax, dt_fixed;
     double E[HB_NTMAX * HB_NTMAX];
     double wall_ut[4][HB_NTMAX], wall_T[4][HB_NTMAX];

@@ -61,6 +61,62 @@ __device__ inline void stv(Ptr p, long off, double v, double ref)
     if constexpr (sizeof(TS) == 4) G(p)[off] = static_cast<float>(v - ref);
     else G(p)[off] = v;
 }
+
+// Buffer resource for raw loads and stores at a wave-uniform base (the first
+// lane's address, moved to scalar registers)
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(T *p)
+{
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)((static_cast<unsigned long long>(hi) << 32) | lo), 0, -1,
+                                             0x00020000);
+}
+
+// How the mixed update writes h^{k+1}, b^{k+1} (a template parameter: the
+// cache policy is an immediate of the store instruction).  OUT_NT: non-temporal
+// stores, for a state larger than the last-level cache (Params::stream_out):
+// the next pass cannot find it there, and cached stores would only evict the
+// stencil the update is still reading.  OUT_BUF: stores through buffer
+// resources at the cell's block (a wave-uniform base, the lane's velocity as
+// the offset), which leaves the single-case kernels fewer address registers;
+// the batched kernels, shorter of scalar registers, keep global stores.
+enum : int { OUT_NT = 1, OUT_BUF = 2 };
+template <int OUT, bool BUF = (OUT & OUT_BUF) != 0>
+struct OutStore;
+template <int OUT>
+struct OutStore<OUT, true> {
+    __amdgpu_buffer_rsrc_t rh, rb;
+    unsigned vo;
+    __device__ OutStore(float *hn, float *bn, long cb, int ap)
+        : rh(uniform_rsrc(hn + cb)), rb(uniform_rsrc(bn + cb)), vo((unsigned)ap * 4u)
+    {
+    }
+    // lw: the level's offset in words from the cell's block
+    __device__ void put(int lw, float h, float b) const
+    {
+        constexpr int pol = (OUT & OUT_NT) ? 2 : 0;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), rh, vo, lw * 4, pol);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, b), rb, vo, lw * 4, pol);
+    }
+};
+template <int OUT>
+struct OutStore<OUT, false> {
+    gptr<float> ph, pb;
+    __device__ OutStore(float *hn, float *bn, long cb, int ap) : ph(G(hn + cb + ap)), pb(G(bn + cb + ap)) {}
+    __device__ void put(int lw, float h, float b) const
+    {
+        if constexpr ((OUT & OUT_NT) != 0) {
+            __builtin_nontemporal_store(h, &ph[lw]);
+            __builtin_nontemporal_store(b, &pb[lw]);
+        } else {
+            ph[lw] = h;
+            pb[lw] = b;
+        }
+    }
+};
+
 template <typename TS>
 __device__ inline double href_of(const Params &P, int ap)
 {
@@ -1349,31 +1405,32 @@ __device__ inline void update_bnd_cell_d(const Params &P, const TS *__restrict__
 #include "hb_mixed.h"
 namespace hb {
 
-// FP64 storage: the FP64 bodies above; mixed storage: the FP32 bodies of hb_mixed.h
-template <int NT, typename TS>
+// FP64 storage: the FP64 bodies above; mixed storage: the FP32 bodies of
+// hb_mixed.h, with the output policy OUT (OutStore).
+template <int NT, typename TS, int OUT>
 __device__ inline void update_int_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                        const double *__restrict__ crec, const double *__restrict__ dtc,
                                        TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int ci)
 {
     if constexpr (sizeof(TS) == 4)
-        update_int_cell_m<NT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, ci);
+        update_int_cell_m<NT, OUT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, ci);
     else
         update_int_cell_d<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, ci);
 }
-template <int NT, typename TS>
+template <int NT, typename TS, int OUT>
 __device__ inline void update_bnd_cell(const Params &P, const TS *__restrict__ h, const TS *__restrict__ b,
                                        const double *__restrict__ recx, const double *__restrict__ recy,
                                        const double *__restrict__ crec, const double *__restrict__ dtc,
                                        TS *__restrict__ hn, TS *__restrict__ bn, double *__restrict__ Wn, int c)
 {
     if constexpr (sizeof(TS) == 4)
-        update_bnd_cell_m<NT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, c);
+        update_bnd_cell_m<NT, OUT>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, c);
     else
         update_bnd_cell_d<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, c);
 }
 
-template <int NT, typename TS>
+template <int NT, typename TS, bool SO = false>
 __global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_WAVES) void k_update_int(Params P, const TS *__restrict__ h,
                                                        const TS *__restrict__ b, const double *__restrict__ recx,
                                                        const double *__restrict__ recy,
@@ -1381,11 +1438,11 @@ __global__ __launch_bounds__(256, sizeof(TS) == 4 ? HB_UPD_WAVES_MIXED : HB_UPD_
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
                                                        TS *__restrict__ bn, double *__restrict__ Wn)
 {
-    update_int_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn,
-                            strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx - 4, P.ny - 4));
+    update_int_cell<NT, TS, (SO ? OUT_NT : 0) | OUT_BUF>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn,
+                                strip_cell(xcd_cell(blockIdx.x, gridDim.x), P.nx - 4, P.ny - 4));
 }
 
-template <int NT, typename TS>
+template <int NT, typename TS, bool SO = false>
 __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__restrict__ cells,
                                                        const TS *__restrict__ h, const TS *__restrict__ b,
                                                        const double *__restrict__ recx, const double *__restrict__ recy,
@@ -1393,7 +1450,7 @@ __global__ __launch_bounds__(256, 2) void k_update_bnd(Params P, const int *__re
                                                        const double *__restrict__ dtc, TS *__restrict__ hn,
                                                        TS *__restrict__ bn, double *__restrict__ Wn)
 {
-    update_bnd_cell<NT, TS>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, cells[xcd_cell(blockIdx.x, gridDim.x)]);
+    update_bnd_cell<NT, TS, (SO ? OUT_NT : 0) | OUT_BUF>(P, h, b, recx, recy, crec, dtc, hn, bn, Wn, cells[xcd_cell(blockIdx.x, gridDim.x)]);
 }
 
 // ---------------------------------------------------------------- set-up kernels

@@ -135,12 +135,14 @@ __device__ inline void build_tables_m(const Params &P, const gptr<const double> 
 // Spectral source and semi-implicit collision (Eq. 30) for one velocity at all
 // levels in FP32, then the store of the deviations of h^{k+1}, b^{k+1} times
 // the level-mass factor s_n: s_n (H_ref + d) - H_ref = s_n d + (s_n - 1) H_ref.
-template <int NT>
+template <int NT, int OUT>
 __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float *ctab, float dG, float dgw,
                                        const Mono &m, float eru, float erv, float href, int iu, int iv,
                                        const float *hk, const float *bk, const float *dh, const float *db,
-                                       float *__restrict__ hn, float *__restrict__ bn, long e0)
+                                       float *__restrict__ hn, float *__restrict__ bn, long cb, int ap)
 {
+    // the cell's block of the outputs (cb: its first word), the lane's velocity ap
+    const OutStore<OUT> out(hn, bn, cb, ap);
     const int M = P.Mt;  // table row stride
     const float kh = P.K - 5.0f;
     cfloat *ls = wave_uniform_f(P.lscale32);
@@ -176,8 +178,7 @@ __device__ inline void collide_store_m(const Params &P, cfloat *cc, const float 
         const float hnum = fmaf(hk[n], om0, fmaf(a1, dheq[1], fmaf(a0, dheq[0], -fmaf(dG, dh[n], dgw * Eh))));
         const float bnum = fmaf(bk[n], om0, fmaf(a1, dbeq[1], fmaf(a0, dbeq[0], -fmaf(dG, db[n], dgw * Eb))));
         const float sn = ls[n], sm = ls[HB_NTMAX + n];  // s_n, (s_n - 1)/pi
-        G(hn)[e0 + (long)n * P.ls] = fmaf(sn, hnum * rden, sm * href);
-        G(bn)[e0 + (long)n * P.ls] = fmaf(sn, bnum * rden, sm * (0.5f * P.K) * href);
+        out.put(n * P.ls, fmaf(sn, hnum * rden, sm * href), fmaf(sn, bnum * rden, sm * (0.5f * P.K) * href));
     }
 }
 
@@ -381,15 +382,6 @@ __device__ inline float vlslope(float d1, float d2, float r1, float r2)
     return p > 0.0f ? q : 0.0f;
 }
 
-// a pointer every lane holds, moved to scalar registers
-__device__ inline const float *uniform_ptr(const float *p)
-{
-    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
-    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
-    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
-    return reinterpret_cast<const float *>((static_cast<unsigned long long>(hi) << 32) | lo);
-}
-
 // Interior cell (2 <= i <= nx-3, 2 <= j <= ny-3) of the mixed form: the
 // straight-line stencil of update_int_cell in FP32.  The stencil is read with
 // buffer loads (one descriptor per array at the cell's lowest stencil element,
@@ -398,7 +390,7 @@ __device__ inline const float *uniform_ptr(const float *p)
 // away from the cell, dA = f_U - f_UU and dB = f_c - f_U, whatever the
 // quadrant: for u < 0 that negates both differences, so the slope changes sign
 // and the sign goes into the constants that multiply it.
-template <int NT>
+template <int NT, int OUT>
 __device__ inline void update_int_cell_m(const Params &P, const float *__restrict__ h, const float *__restrict__ b,
                                          const double *__restrict__ recx, const double *__restrict__ recy,
                                          const double *__restrict__ crec, const double *__restrict__ dtc,
@@ -435,8 +427,8 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
                 *ryn = P.ry32 + fn * REC32;
     // the stencil of an interior cell reaches two rows down at most
     const long lo = (long)c * NT * P.ls - 2 * sy;
-    const __amdgpu_buffer_rsrc_t rsh = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(h + lo), 0, -1, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(b + lo), 0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsh = uniform_rsrc(h + lo);
+    const __amdgpu_buffer_rsrc_t rsb = uniform_rsrc(b + lo);
     // the folded van Leer constants 2 r1 r2 of the cell's own slopes
     const float kx = 2.0f * rx1 * rx2, ky = 2.0f * ry1 * ry2;
 
@@ -465,7 +457,6 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
         // |u| rdx, |v| rdy: the divergence is |u| (g_downwind - g_upwind) / dx + ...
         const float aur = fabsf(u) * rdx, avr = fabsf(v) * rdy;
         float hk[NT], bk[NT], dh[NT], db[NT];
-        const long e0 = (long)c * NT * P.ls + ap;
         const unsigned vo = (unsigned)ap * 4u;
         struct Lv {
             float hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUU, bUU, hUs, bUs, hUn, bUn, hVV, bVV, hVw, bVw, hVe, bVe;
@@ -540,14 +531,14 @@ __device__ inline void update_int_cell_m(const Params &P, const float *__restric
             // scheduler's interleaving across levels measured slower there)
             if constexpr (NT <= 5) __builtin_amdgcn_sched_barrier(0);
         }
-        collide_store_m<NT>(P, cc, ctab, dG, dgw, m, eru, erv, href, iu, iv, hk, bk, dh, db, hn, bn, e0);
+        collide_store_m<NT, OUT>(P, cc, ctab, dG, dgw, m, eru, erv, href, iu, iv, hk, bk, dh, db, hn, bn, (long)c * NT * P.ls, ap);
     }
 }
 
 // Cells within two of a wall in the mixed form: update_bnd_cell in FP32, with
 // one-sided wall slopes and the diffuse-wall inflow (the wall side of a wall
 // face has c4 = c5 = 0 in its record, so its face value does not enter).
-template <int NT>
+template <int NT, int OUT>
 __device__ inline void update_bnd_cell_m(const Params &P, const float *__restrict__ h, const float *__restrict__ b,
                                          const double *__restrict__ recx, const double *__restrict__ recy,
                                          const double *__restrict__ crec, const double *__restrict__ dtc,
@@ -583,8 +574,8 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
     // two rows below the cell (the lowest element a ring stencil can reach; the
     // descriptor's base may lie below the array, every address read is inside)
     const long lo = (long)c * NT * P.ls - 2 * sy;
-    const __amdgpu_buffer_rsrc_t rsh = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(h + lo), 0, -1, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(b + lo), 0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsh = uniform_rsrc(h + lo);
+    const __amdgpu_buffer_rsrc_t rsb = uniform_rsrc(b + lo);
 
     for (int ap = threadIdx.x; ap < P.nvp; ap += blockDim.x) {
         const int r = ap % P.Qp;
@@ -614,7 +605,6 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
         const float rUm = G(P.rcx)[iUc], rUp = G(P.rcx)[iUc + 1], rVm = G(P.rcy)[jVc], rVp = G(P.rcy)[jVc + 1];
         const float aur = fabsf(u) * rdx, avr = fabsf(v) * rdy;
         float hk[NT], bk[NT], dh[NT], db[NT];
-        const long e0 = (long)c * NT * P.ls + ap;
         const unsigned vo = (unsigned)ap * 4u;
         struct Lv {
             float hc, bc, hW, bW, hE, bE, hS, bS, hN, bN, hUF, bUF, hUs, bUs, hUn, bUn, hVF, bVF, hVw, bVw, hVe, bVe;
@@ -698,7 +688,7 @@ __device__ inline void update_bnd_cell_m(const Params &P, const float *__restric
             db[n] = fmaf(aur, gxo_b - gxi_b, avr * (gyo_b - gyi_b));
             __builtin_amdgcn_sched_barrier(0);
         }
-        collide_store_m<NT>(P, cc, ctab, dG, dgw, m, eru, erv, href, iu, iv, hk, bk, dh, db, hn, bn, e0);
+        collide_store_m<NT, OUT>(P, cc, ctab, dG, dgw, m, eru, erv, href, iu, iv, hk, bk, dh, db, hn, bn, (long)c * NT * P.ls, ap);
     }
 }
 
