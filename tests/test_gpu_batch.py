@@ -132,3 +132,21 @@ def test_tuned_shapes_keep_results(hb):
     for (case, prec), h in zip(CASES, bc):
         assert _same(h.state(), _solo(hb, case, prec, 5)[0])
     B.close()
+
+
+def test_streaming_store_case_matches_solo(hb):
+    """A mixed case whose state exceeds 128 MiB (48^2 cells x 48^2 velocities x
+    9 levels: 382 MB of FP32 h and b) stores its update non-temporally, in the
+    single-case kernels through buffer resources and in the batched ones
+    through global stores; beside a small cached-store case in one batch it
+    must still give the bits it gives alone."""
+    big = Case(48, 48, 48, 5.0, 1.0, 1.0, 4, hbcases.thermal_walls(0.5, 0, "sin"))
+    small = CASES[1]
+    assert big.nc * big.NT * 4 * 576 * 2 * 4 > 128 << 20
+    B = hb.Batch(max_cases=2, pool_bytes=2 << 30)
+    hb_big = B.add(big, hb.HB_MIXED)
+    hb_small = B.add(*small)
+    B.step(4)
+    assert _same(hb_big.state(), _solo(hb, big, hb.HB_MIXED, 4)[0])
+    assert _same(hb_small.state(), _solo(hb, *small, 4)[0])
+    B.close()
