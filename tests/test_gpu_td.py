@@ -54,9 +54,12 @@ def _perturbed(oracle_mod, case, seed, amp=0.05):
     return W, h, b
 
 
+@pytest.mark.parametrize("grid", [{}, dict(Mv=16, vmax=5.5)], ids=["square", "rect12x16"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)], ids=["fp64", "mixed"])
-def test_td_steps_match_oracle(gpu, oracle_mod, prec, tol):
-    case = _ragged_td(1.2e-3)
+def test_td_steps_match_oracle(gpu, oracle_mod, prec, tol, grid):
+    """The ragged heated case (12^2 velocities on [-4.5, 4.5], or 12 along u and
+    16 on [-5.5, 5.5] along v) after 1, 4 and 30 time-domain steps."""
+    case = _ragged_td(1.2e-3).with_(**grid)
     st = _perturbed(oracle_mod, case, 404)
     o = oracle_mod.Oracle(case, td=True)
     rest = [x.copy() for x in o.state()]  # the uniform rest state: the signal is the deviation from it
