@@ -262,12 +262,15 @@ def td_step_size(hb, case):
     period holds a whole number of steps.  Returns (dt, steps per period)."""
     import numpy as np
     u, _ = hb.hb_vgrid_nodes(case.M, case.umax, case.vrule)
+    v, _ = hb.hb_vgrid_nodes(case.Mv_, case.vmax_, case.vrule)
     gamma = (case.K + 4.0) / (case.K + 2.0)
     t_max = max(w[3] + np.hypot(w[4], w[5]) for w in case.walls)  # hottest wall, in T0
-    ut = max(abs(u[0]), abs(u[-1])) + np.sqrt(gamma * max(1.0, t_max) / 2.0)
+    cs = np.sqrt(gamma * max(1.0, t_max) / 2.0)
+    ut = max(abs(u[0]), abs(u[-1])) + cs
+    vt = max(abs(v[0]), abs(v[-1])) + cs
     dx = np.diff(case.x_faces) if case.x_faces is not None else np.full(case.nx, case.L / case.nx)
     dy = np.diff(case.y_faces) if case.y_faces is not None else np.full(case.ny, case.H / case.ny)
-    nu = ut / dx.min() + ut / dy.min()
+    nu = ut / dx.min() + vt / dy.min()
     period = 2.0 * np.pi / case.St
     ns = int(np.ceil(period * nu / case.cfl))
     return period / ns, ns
