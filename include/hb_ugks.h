@@ -138,8 +138,9 @@ int hb_ugks_create(const hb_create_opts *opts, hb_handle *out);
  * (rho = 1, U = 0, T = T0 at every level).  Kn (Eq. 36) and St (Eq. 37) set
  * mu(T0) and omega; n_harmonics = NH gives NT = 2 NH + 1 levels (NT <= 11).
  * walls: 4 entries; num: NULL = defaults.  Allocates the device state.
- * Errors: HB_EINVAL (sizes, Kn <= 0, St < 0, odd m, non-increasing faces,
- * cfl <= 0), HB_ENOMEM, HB_EDEVICE. */
+ * Errors: HB_EINVAL (sizes, Kn <= 0, St < 0, odd m or m_v, non-increasing
+ * faces, cfl <= 0, or update tables of 16 NT max(m, m_v) words (8 B in FP64,
+ * 4 B mixed) above the 160 KB of LDS), HB_ENOMEM, HB_EDEVICE. */
 int hb_ugks_set_case(hb_handle h, const hb_geometry *geo, double Kn, double St, int n_harmonics,
                      const hb_wall walls[4], const hb_vgrid *vg, const hb_numerics *num);
 
