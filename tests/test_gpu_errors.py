@@ -8,6 +8,8 @@
 - HB_ECAPACITY: buffers shorter than the result for harmonics_out and
   state_out.
 - HB_ESTATE: stepping, reading or copying before set_case.
+- HB_EINVAL for a velocity grid whose v axis is odd, too short or too long,
+  or whose update tables (16 N_T max(M, M_v) words) exceed the LDS.
 No error here comes from a device fault: every kernel runs to its end (a NaN
 is ordinary floating-point data to them)."""
 import ctypes
@@ -123,3 +125,28 @@ def test_calls_before_set_case(gpu):
     assert L.hb_ugks_state_out(h, out.ctypes.data_as(dp), None, None, 0) == gpu.HB_ESTATE
     assert L.hb_ugks_pseudo_step(h, -1) == gpu.HB_ESTATE
     gpu.hb_ugks_destroy(h)
+
+
+@pytest.mark.parametrize("grid,prec,ok", [
+    (dict(Mv=7), 0, False),                 # odd node count along v
+    (dict(Mv=-2), 0, False),
+    (dict(Mv=2), 1, False),                 # fewer than 4 nodes
+    (dict(Mv=130), 1, False),               # more than 128
+    (dict(M=16, Mv=128, NH=5), 0, False),   # FP64 tables 16 x 11 x 128 x 8 B = 180 KB > 160 KB of LDS
+    (dict(M=16, Mv=128, NH=5), 1, True),    # the same tables in FP32: 90 KB
+], ids=["odd", "negative", "two", "130", "fp64-lds", "mixed-lds"])
+def test_rectangular_grid_arguments(gpu, grid, prec, ok):
+    """hb_vgrid's v axis is checked like the u axis, and the update tables'
+    size bound takes the longer axis."""
+    case = _small().with_(**grid)
+    h = gpu.hb_ugks_create(precision=prec)
+    try:
+        if ok:
+            gpu.hb_ugks_set_case(h, case)
+            assert gpu.hb_ugks_sizes(h)[4] == case.M * case.Mv
+        else:
+            with pytest.raises(gpu.HBError) as e:
+                gpu.hb_ugks_set_case(h, case)
+            assert e.value.code == gpu.HB_EINVAL
+    finally:
+        gpu.hb_ugks_destroy(h)
