@@ -169,6 +169,23 @@ def test_rectangular_grid_layout_and_rest_state(oracle_mod):
     np.testing.assert_allclose(o.state()[1], h0, atol=1e-14)
 
 
+def test_local_step_takes_each_axis_extent(oracle_mod):
+    """Eq. (32) at rest on a rectangular velocity grid (10 nodes on [-4, 4]
+    along u, 14 on [-6, 6] along v) and non-uniform cells: the local step is
+    CFL / ((u_max + c_s)/dx + (v_max + c_s)/dy + omega N_H), c_s = sqrt(gamma/2),
+    with each axis's own extent against its own cell width."""
+    xf = (0.0, 0.1, 0.3, 0.6, 0.8, 1.0)
+    yf = (0.0, 0.2, 0.35, 0.5, 0.75, 0.9, 1.0)
+    c = Case(5, 6, 10, 4.0, 0.5, 1.5, 2, hbcases.REST_WALLS, x_faces=xf, y_faces=yf, Mv=14, vmax=6.0)
+    o = oracle_mod.Oracle(c)
+    o.step(1)
+    dtc, _, _ = o.debug()
+    cs = np.sqrt((c.K + 4.0) / (c.K + 2.0) / 2.0)
+    dx, dy = np.diff(xf), np.diff(yf)
+    want = c.cfl / ((4.0 + cs) / dx[None, :] + (6.0 + cs) / dy[:, None] + c.St * c.NH)
+    np.testing.assert_allclose(dtc.reshape(c.ny, c.nx), want, rtol=1e-14)
+
+
 def test_harmonics_of_a_known_state(oracle_mod):
     """Eq. (40): qhat_k = (1/NT) sum_n q_n exp(-i k w t_n).  A state whose
     levels carry rho_n = 1 + A cos(w t_n + phi) has rhohat_1 = (A/2) e^{i phi}."""
