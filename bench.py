@@ -18,7 +18,9 @@ Prints one JSON line (stdout).  Progress goes to stderr.
                   [--first I] [--count N] [--cap S] [--requests N] [--rate R] [--td-cap S]
 Besides the headline, the JSON line carries: the headline case's one-step
 error against the FP64 oracle at full size, the oracle timed on the host
-(all threads and one), the time to converge from rest, the 64 x 64-cell,
+(all threads and one), the time to converge from rest, the 16 x 16-cell FP64
+correctness case solved to convergence on the GPU and by the oracle (wall
+times and converged harmonics against each other), the 64 x 64-cell,
 32 x 32-velocity, N_H = 1 shear cavity in both forms, per-step times over
 the Kn x St grids, and the 64-case batched sweep.
 """
@@ -411,6 +413,50 @@ def timed_median(hb, case, prec, stream, sync, steps, warmup, reps=3):
     return sorted(t)[len(t) // 2]
 
 
+def small_full_solve(hb, hbcases, oracle_mod, stream, sync, tol=1e-8, chunk=100, max_steps=200000, cap_s=120.0):
+    """The FP64 correctness case (16^2 cells, 16^2 velocities on [-4, 4], BGK,
+    N_H = 1, Kn = St = 1) solved from rest to R_rho <= tol on the GPU, and, with
+    oracle_mod given, by the oracle on this host's cores (its CPU baseline for
+    a full solve); then the converged harmonics of the two against each other,
+    per variable: the largest difference over the variable's largest |q_k|, k >= 1."""
+    import numpy as np
+    case = hbcases.shear_small()
+
+    def solve(step, residual):
+        t0 = time.perf_counter()
+        k, r = 0, float("inf")
+        while k < max_steps and time.perf_counter() - t0 < cap_s:
+            step(chunk)
+            k += chunk
+            r = residual()
+            if r <= tol:
+                break
+        return k, r, time.perf_counter() - t0
+
+    s = hb.Solver(case, device=0, stream=stream)
+    k, r, t = solve(s.step, lambda: s.residual()[0])
+    if sync:
+        sync()
+    re_g, im_g = s.harmonics()
+    s.close()
+    out = {"workload": case.name, "precision": "fp64", "tol": tol,
+           "gpu": {"steps": k, "residual": r, "converged": bool(r <= tol), "wall_s": t}}
+    if oracle_mod is not None:
+        o = oracle_mod.Oracle(case)
+        ko, ro, to = solve(o.step, lambda: o.residual()[0])
+        re_o, im_o = o.harmonics()
+        out["cpu_oracle"] = {"steps": ko, "residual": ro, "converged": bool(ro <= tol), "wall_s": to,
+                             "cores": oracle_mod.threads(), "kind": "oracle", "host": host_cpu()}
+        names = ("rho", "U", "V", "T", "P_xy", "q_x", "q_y")
+        err = {}
+        for v, nm in enumerate(names):
+            sig = np.max(np.hypot(re_o[v, 1:], im_o[v, 1:]))
+            d = np.max(np.hypot(re_g[v] - re_o[v], im_g[v] - im_o[v]))
+            err[nm] = float(d / sig) if sig > 0 else None
+        out["harmonics_rel_err_gpu_vs_oracle"] = err
+    return out
+
+
 def host_cpu():
     """CPU model and logical CPUs of this host (for the oracle baseline)."""
     model = None
@@ -634,6 +680,16 @@ def main():
             conv["cpu_oracle_wall_s_extrapolated"] = k * cpu_step
         log(f"converge: {k} steps to R_rho {r:.2e} in {tconv:.2f} s")
 
+    # the correctness case: a full solve on the GPU and by the oracle on the host
+    small = None
+    if not args.no_extra:
+        small = small_full_solve(hb, hbcases, None if args.no_cpu else oracle, stream, sync)
+        g = small["gpu"]
+        log(f"correctness case {small['workload']}: GPU {g['steps']} steps to R_rho {g['residual']:.2e} in "
+            f"{g['wall_s']:.2f} s" + (f"; oracle {small['cpu_oracle']['steps']} steps in "
+                                       f"{small['cpu_oracle']['wall_s']:.1f} s; harmonics "
+                                       f"{small['harmonics_rel_err_gpu_vs_oracle']}" if "cpu_oracle" in small else ""))
+
     extra = []
     if not args.no_extra:
         others = []
@@ -699,6 +755,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
         "converge": conv,
+        "correctness_case_full_solve": small,
         "kn_st_sweep": knst,
         "other_workloads": extra,
         "batched": batched,
