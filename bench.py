@@ -713,6 +713,24 @@ def main():
                           "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 2) for k, (n, ms) in kt2.items()},
                           "roofline": roofline(d2, kt2[d2], a2, traffic_bytes(c2.name, pname, d2))})
             log(f"extra {c2.name} {pname}: ms/step {ms2:.4f} updates/s {c2.updates / (ms2 * 1e-3):.4e}")
+            if c2.name.startswith("shear64") and p2 == hb.HB_FP64:
+                # a full solve of this case from rest (residual read every 100 steps, capped at 60 s)
+                s2 = hb.Solver(c2, device=0, stream=stream, precision=p2)
+                t0 = time.perf_counter()
+                k2, r2 = 0, float("inf")
+                while k2 < 200000 and time.perf_counter() - t0 < 60.0:
+                    s2.step(100)
+                    k2 += 100
+                    r2 = s2.residual()[0]
+                    if r2 <= 1e-8:
+                        break
+                t2 = time.perf_counter() - t0
+                s2.close()
+                extra[-1]["converge"] = {"tol": 1e-8, "steps": k2, "residual": r2, "converged": bool(r2 <= 1e-8),
+                                         "wall_s": t2, "wall_cap_s": 60.0}
+                if cpu is not None:  # the oracle's rate on the headline case, applied to these steps
+                    extra[-1]["converge"]["cpu_oracle_wall_s_extrapolated"] = k2 * c2.updates / cpu["value"]
+                log(f"extra {c2.name} {pname}: converge {k2} steps to R_rho {r2:.2e} in {t2:.2f} s")
 
     # per-step time over the Kn x St grids of the shear and thermal cases (the arithmetic per step does not
     # depend on them)
